@@ -1,0 +1,200 @@
+/*
+ * fpcg.h -- C ABI of the MI355X (gfx950) finite-precision block-Jacobi CG
+ * massive-MIMO detector (arXiv 2504.09820).
+ *
+ * The library computes, for every channel c of a batch and every received
+ * vector y_n of that channel,
+ *     A = H^H H + sigma^2 I,  b_n = H^H y_n           (Sec. II, eq. inversion)
+ *     x_n ~= A^{-1} b_n by I iterations of FP-CG       (Alg. 2) or
+ *     of FP-BJ-CG with L x L block-Jacobi blocks       (eq. pre_BJ, Alg. 3)
+ * in the precisions of an fpcg_schedule, then slices x_n to square-QAM
+ * hard decisions with Gray labels.
+ *
+ * Conventions shared by every call
+ *   - Complex arrays are interleaved (re, im), C order.  io_c64 != 0 means
+ *     complex64 (float2) elements, otherwise complex128 (double2).
+ *   - H is (B, Nbs, K): H[c][a][k] is the gain from stream k to antenna a.
+ *     Y is (B, Nbs, R): R received vectors per channel sharing that H.
+ *     xhat is (B, K, R) in the same element type as H and Y; labels is
+ *     (B, K, R) uint8; flags is (B) uint32; sigma2 is (B) double.
+ *   - Device pointers are memory of the device the context was created on.
+ *     The caller allocates and frees them; the library never frees or keeps
+ *     caller memory beyond the asynchronous work it enqueued.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     asynchronously; results are valid once the stream reaches that point.
+ *   - Argument errors are returned synchronously, before anything is enqueued.
+ *     Numerical outcomes are never call errors: they are reported per channel
+ *     through the flag bits below.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef FPCG_H
+#define FPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FPCG_OK = 0,
+    FPCG_E_INVAL = -1,        /* bad argument (null pointer, size, order, L not dividing K, ...) */
+    FPCG_E_NOMEM = -2,        /* request does not fit the context's device-memory budget        */
+    FPCG_E_DEVICE = -3,       /* a HIP runtime call failed                                      */
+    FPCG_E_UNSUPPORTED = -4,  /* valid but not built (e.g. K > 64, schedule combination)        */
+    FPCG_E_BUSY = -5          /* serving queue full                                             */
+} fpcg_status;
+
+/* Number formats (Table I of the paper, plus OCP fp8 e4m3 "fn"). */
+typedef enum {
+    FPCG_F64 = 0,
+    FPCG_F32 = 1,
+    FPCG_BF16 = 2,
+    FPCG_F16 = 3,
+    FPCG_F8E4M3 = 4
+} fpcg_fmt;
+
+/* Per-channel flag bits written to flags[c]. */
+enum {
+    FPCG_FLAG_NONFINITE = 1,     /* A or b had a non-finite entry; x_hat = 0 for the channel   */
+    FPCG_FLAG_BREAKDOWN = 2,     /* phi <= 0 or rho <= 0 (or not finite) froze a column         */
+    FPCG_FLAG_BLOCK_NOT_PD = 4,  /* a Jacobi block was not positive definite: diagonal inverse   */
+    FPCG_FLAG_FP8_SAT = 8        /* an fp8 operand was not finite after scaling                  */
+};
+
+/*
+ * Precision schedule.  Alg. 2 and Alg. 3 run the matrix-vector product A p at
+ * u_MV, the inner products at u_IP and every other step at u_W.
+ *   gram_op : format H and y are rounded to before the Gram / matched filter
+ *   mv_op   : u_MV, format of the A and p operands of A p (accumulated in
+ *             FP32, or FP64 when mv_op = F64)
+ *   ip      : u_IP (must equal work)
+ *   work    : u_W: F64 (all-FP64 path) or F32
+ *   refresh_every : every k-th iteration replace r by b - A x computed in FP64
+ *             on the stored Gram (0 = off)
+ *   refine_steps  : FP64 iterative refinement steps: r = H^H (y - H x) -
+ *             sigma^2 x in FP64, solve A d = r with the same schedule, x += d
+ *   variant : 0 = Alg. 3 as printed (rho = r^H p); 1 = textbook PCG (r^H z)
+ * Built combinations: gram_op == mv_op, and work = ip = (mv_op == F64 ? F64 : F32).
+ */
+typedef struct {
+    int32_t gram_op;
+    int32_t mv_op;
+    int32_t ip;
+    int32_t work;
+    int32_t refresh_every;
+    int32_t refine_steps;
+    int32_t variant;
+} fpcg_schedule;
+
+typedef struct fpcg_ctx fpcg_ctx;
+
+/* Create a context on HIP device `device`.  `hbm_budget` bounds the device
+ * memory the serving queue may hold for in-flight requests (0 = 80 % of the
+ * free memory at creation).  Returns FPCG_E_DEVICE if the device is absent. */
+fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out);
+
+/* Waits for the context's own streams, then frees everything it owns. */
+void fpcg_destroy(fpcg_ctx* ctx);
+
+/* Static description of a status code. */
+const char* fpcg_strerror(int32_t status);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* fpcg_last_error(void);
+
+/* Host-only validation of a detect() configuration (no device needed).
+ * Returns FPCG_OK, FPCG_E_INVAL or FPCG_E_UNSUPPORTED exactly as
+ * fpcg_detect would for the same sizes and schedule. */
+fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam_order,
+                       int32_t iters, int32_t block_L, const fpcg_schedule* sched);
+
+/*
+ * The detector (Sec. II, Alg. 2 / Alg. 3): Gram and matched filter on the
+ * matrix cores, block-Jacobi setup, `iters` (P)CG iterations, optional FP64
+ * refresh / refinement, QAM slicer.  One fused kernel; nothing but inputs
+ * and outputs touches device memory.
+ *   B >= 0 channels (B = 0 is a no-op); Nbs >= 1; 1 <= K <= 64; R >= 1.
+ *   qam_order in {4, 16, 64, 256}; iters >= 0 (0 gives x_hat = 0).
+ *   block_L = 0: Alg. 2 (no preconditioner); block_L in {4, 8}: Alg. 3,
+ *   block_L must divide K and be <= the padded K / 4.
+ *   sched = NULL means the all-FP64 schedule.
+ *   flags may be NULL.
+ */
+fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream,
+                        int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                        const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                        int32_t qam_order, int32_t iters, int32_t block_L,
+                        const fpcg_schedule* sched,
+                        void* xhat, uint8_t* labels, uint32_t* flags);
+
+/* QAM slicer on its own (the detector's epilogue): nearest unit-energy
+ * square-QAM point per complex value, decided in FP32 (x_c64 != 0) or FP64.
+ * Per axis j = clamp(floor((v nu + m) / 2), 0, m - 1), nu = sqrt(2 (Q-1) / 3),
+ * label = (gray(j_I) << log2 m) | gray(j_Q).  n >= 0 values, device pointers. */
+fpcg_status fpcg_slice(void* stream, int64_t n, const void* x, int32_t x_c64,
+                       int32_t qam_order, uint8_t* labels);
+
+/* Operand rounding used by the detector (the fl(.) operator of Def. 1):
+ * out[i] = fmt(in[i] * scale) / scale with round-to-nearest-even, for fmt in
+ * {F32, BF16, F16, F8E4M3}; `scale` must be a power of two.  n >= 0 floats,
+ * device pointers (in-place allowed). */
+fpcg_status fpcg_round(void* stream, int64_t n, const float* in, int32_t fmt, float scale, float* out);
+
+/* Precision heuristic (eq. heuristic / eq. heuristic_bj): u_bound =
+ * 1 / (N^1.5 sqrt(kappa)); *fmt = the cheapest format whose unit roundoff is
+ * below it (fp8 only if allow_fp8; fp16 preferred over bf16).  Host only. */
+fpcg_status fpcg_select_precision(int32_t N, double kappa, int32_t allow_fp8,
+                                  int32_t* fmt, double* u_bound);
+
+/* ------------------------------------------------------------------ serving
+ * A continuous-batching request loop.  Requests carry host buffers; the
+ * server admits a request when its device footprint fits the context's
+ * budget and a stream slot is free, copies it in, runs fpcg_detect on that
+ * slot's stream and copies the results back.  Requests that arrive while
+ * others run are admitted as memory and slots free up, so their work overlaps
+ * on the device.  Every channel is computed by its own workgroup in a fixed
+ * order, so a request's result is bitwise the same alone and in any mix. */
+typedef struct {
+    int64_t B;
+    int32_t Nbs, K, R;
+    int32_t io_c64;
+    int32_t qam_order, iters, block_L;
+    fpcg_schedule sched;
+    const void* H;        /* host */
+    const void* Y;        /* host */
+    const double* sigma2; /* host */
+    void* xhat;           /* host, written on completion */
+    uint8_t* labels;      /* host, written on completion */
+    uint32_t* flags;      /* host, written on completion (may be NULL) */
+} fpcg_request;
+
+typedef struct fpcg_server fpcg_server;
+
+/* n_slots concurrent streams (1..16), queue_cap pending requests (>= 1). */
+fpcg_status fpcg_server_create(fpcg_ctx* ctx, int32_t n_slots, int32_t queue_cap, fpcg_server** out);
+
+/* Enqueue a request (validated synchronously).  The host buffers must stay
+ * valid until fpcg_poll reports completion.  FPCG_E_BUSY if the queue is
+ * full, FPCG_E_NOMEM if the request alone exceeds the budget. */
+fpcg_status fpcg_submit(fpcg_server* srv, const fpcg_request* req, uint64_t* ticket);
+
+/* Advance the server (admit, launch, retire) and report whether `ticket` is
+ * done (1) or not yet (0).  Never blocks. */
+fpcg_status fpcg_poll(fpcg_server* srv, uint64_t ticket, int32_t* done);
+
+/* Advance until every submitted request has completed. */
+fpcg_status fpcg_drain(fpcg_server* srv);
+
+/* In-flight requests, queued requests and device bytes held right now. */
+fpcg_status fpcg_server_stats(fpcg_server* srv, int32_t* in_flight, int32_t* queued, size_t* bytes_held);
+
+/* Drains, then frees the server. */
+void fpcg_server_destroy(fpcg_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPCG_H */

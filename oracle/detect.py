@@ -34,6 +34,8 @@ Readings where the paper is silent (also listed in the design doc):
            core); u_W updates x, r, p use one rounding per fused multiply-add.
   R-fp8    fp8 e4m3 operands carry power-of-two scales: one per channel for
            H and for A, one per column for Y and for p.
+  R-conv   H and y reach a reduced-precision operand format through fp32
+           (rounded to fp32 first, then to the operand format).
   R-refr   FP64 refresh: every k iterations r <- b - A x in FP64 arithmetic on
            the stored Gram (k-th, 2k-th, ... iteration, not the last one).
   R-refi   FP64 refinement: r = H^H (y - H x) - sigma^2 x in FP64, scaled per
@@ -76,6 +78,14 @@ class Schedule:
     refine_steps  : FP64 iterative-refinement steps through H (0 = off)
     variant : 0 = Alg. 3 as printed (rho = r^H p); 1 = textbook PCG (rho = r^H z)
     fma     : u_W updates of the form a*b + c rounded once (True) or twice
+    accum   : "exact": every matrix / inner product is summed exactly and rounded
+              once (an idealised matrix core); "sequential": the same sums as a
+              chain of fused multiply-adds in the accumulation format, in index
+              order; for fp8 operands, groups of 8 products summed with a
+              truncating fixed-point alignment 13 bits below the group's
+              largest product before each rounding (a second valid rounding
+              order, used to measure how sensitive the iterates are to the
+              order and granularity of rounding)
     """
     gram_op: str = "fp64"
     mv_op: str = "fp64"
@@ -86,6 +96,7 @@ class Schedule:
     refine_steps: int = 0
     variant: int = 0
     fma: bool = True
+    accum: str = "exact"
 
 
 FP64 = Schedule()
@@ -128,6 +139,77 @@ def _zeros(b):
     return np.zeros_like(b)
 
 
+def _fma(a, b, c, fmt):
+    """fl(a*b + c) with one rounding into fmt (a*b is exact in fp64 for operands
+    of at most 26 significand bits; in fp64 itself this is two roundings)."""
+    if fmt == "fp64":
+        return a * b + c
+    return round_real(a * b + c, fmt)
+
+
+def _seq_dot_re(u, v, fmt):
+    """Re(u^H v) over axis -2 as an ordered chain of fused multiply-adds."""
+    ur, ui, vr, vi = np.real(u), np.imag(u), np.real(v), np.imag(v)
+    s = np.zeros(u.shape[:-2] + (1, u.shape[-1]))
+    for k in range(u.shape[-2]):
+        s = _fma(ur[..., k:k + 1, :], vr[..., k:k + 1, :], s, fmt)
+        s = _fma(ui[..., k:k + 1, :], vi[..., k:k + 1, :], s, fmt)
+    return s
+
+
+def _trunc_group_sum(terms, frac_bits):
+    """Sum of a group of products aligned to the largest one: every product is
+    truncated toward zero to a multiple of 2^(E - frac_bits), E the exponent of
+    the largest |product| of the group, and the truncated values are added
+    exactly."""
+    mx = np.max(np.abs(terms), axis=0)
+    _, e2 = np.frexp(np.where(mx > 0, mx, 1.0))
+    q = np.ldexp(1.0, (e2 - 1 - frac_bits).astype(np.int64))
+    return np.sum(np.trunc(terms / q) * q, axis=0)
+
+
+def _seq_matmul_grouped(A, P, fmt, group=8, frac_bits=13):
+    """A @ P (complex) accumulated group by group: 8 consecutive products of
+    one real plane are summed with a truncating fixed-point alignment, then
+    added to the accumulator with one rounding.  A valid rounding of the same
+    sums whose error bound is that of an fp8 matrix core."""
+    ar, ai, pr, pi = np.real(A), np.imag(A), np.real(P), np.imag(P)
+    shp = A.shape[:-1] + (P.shape[-1],)
+    wr = np.zeros(shp)
+    wi = np.zeros(shp)
+    K = A.shape[-1]
+    for k0 in range(0, K, group):
+        ks = range(k0, min(K, k0 + group))
+        t_rr = np.stack([ar[..., :, k:k + 1] * pr[..., k:k + 1, :] for k in ks])
+        t_ii = np.stack([-ai[..., :, k:k + 1] * pi[..., k:k + 1, :] for k in ks])
+        t_ir = np.stack([ai[..., :, k:k + 1] * pr[..., k:k + 1, :] for k in ks])
+        t_ri = np.stack([ar[..., :, k:k + 1] * pi[..., k:k + 1, :] for k in ks])
+        wr = round_real(wr + _trunc_group_sum(t_rr, frac_bits), fmt)
+        wr = round_real(wr + _trunc_group_sum(t_ii, frac_bits), fmt)
+        wi = round_real(wi + _trunc_group_sum(t_ir, frac_bits), fmt)
+        wi = round_real(wi + _trunc_group_sum(t_ri, frac_bits), fmt)
+    return wr + 1j * wi
+
+
+def _seq_matmul(A, P, fmt, grouped=False):
+    """A @ P (complex) as ordered chains of real fused multiply-adds over k
+    (grouped=True: the fp8 matrix-core style grouped accumulation)."""
+    if grouped:
+        return _seq_matmul_grouped(A, P, fmt)
+    ar, ai, pr, pi = np.real(A), np.imag(A), np.real(P), np.imag(P)
+    shp = A.shape[:-1] + (P.shape[-1],)
+    wr = np.zeros(shp)
+    wi = np.zeros(shp)
+    for k in range(A.shape[-1]):
+        a_r, a_i = ar[..., :, k:k + 1], ai[..., :, k:k + 1]
+        p_r, p_i = pr[..., k:k + 1, :], pi[..., k:k + 1, :]
+        wr = _fma(a_r, p_r, wr, fmt)
+        wr = _fma(-a_i, p_i, wr, fmt)
+        wi = _fma(a_i, p_r, wi, fmt)
+        wi = _fma(a_r, p_i, wi, fmt)
+    return wr + 1j * wi
+
+
 class _Prec:
     """Rounding hooks for one schedule (identity in exact / fp64 mode)."""
 
@@ -153,6 +235,8 @@ class _Prec:
 
     def ip(self, u, v):
         """Re(u^H v) per column at u_IP (exact sum, one rounding)."""
+        if self.s.accum == "sequential" and not _is_exact(u):
+            return _seq_dot_re(u, v, self.s.ip)
         d = _re(np.sum(np.conj(u) * v, axis=-2, keepdims=True))
         return d if _is_exact(d) else fl(d, self.s.ip)
 
@@ -168,8 +252,12 @@ class MatVec:
 
     def __init__(self, A, sched: Schedule, flags=None):
         self.s = sched
-        self.exact = _is_exact(A) or sched.mv_op == "fp64"
+        self.exact = _is_exact(A) or (sched.mv_op == "fp64" and sched.accum == "exact")
+        self.sA = None
         if self.exact:
+            self.A = A
+            return
+        if sched.mv_op == "fp64":
             self.A = A
             return
         if sched.mv_op == "e4m3":
@@ -182,6 +270,11 @@ class MatVec:
             self.sA = None
             self.A = fl(A, sched.mv_op)
 
+    def _prod(self, A, P):
+        if self.s.accum == "sequential":
+            return _seq_matmul(A, P, self.s.acc, grouped=self.s.mv_op == "e4m3")
+        return fl(A @ P, self.s.acc)
+
     def __call__(self, p):
         if self.exact:
             return self.A @ p
@@ -189,8 +282,8 @@ class MatVec:
             amax = np.max(np.maximum(np.abs(p.real), np.abs(p.imag)), axis=-2, keepdims=True)
             sp = pow2_scale(amax)
             pq = fl(p * sp, "e4m3")
-            return fl(self.A @ pq, self.s.acc) / (self.sA * sp)
-        return fl(self.A @ fl(p, self.s.mv_op), self.s.acc)
+            return self._prod(self.A, pq) / (self.sA * sp)
+        return self._prod(self.A, fl(p, self.s.mv_op))
 
 
 # --------------------------------------------------------------------------
@@ -211,9 +304,23 @@ def gram(H, Y, sigma2, sched: Schedule = FP64):
     eye = np.eye(K)
     if sched.gram_op == "fp64":
         Hh = np.conj(np.swapaxes(H, -1, -2))
+        if sched.accum == "sequential":
+            A = _hermitian_from_upper(_seq_matmul(Hh, H, "fp64")) + s2 * eye
+            B = _seq_matmul(Hh, Y, "fp64")
+            return A, B
         A = Hh @ H + s2 * eye
         B = Hh @ Y
         return A, B
+    # R-conv: inputs reach the operand formats through fp32 (as the hardware
+    # conversion instructions do)
+    H = fl(H, "fp32")
+    Y = fl(Y, "fp32")
+
+    def prod(X, Z):
+        if sched.accum == "sequential":
+            return _seq_matmul(X, Z, sched.acc, grouped=sched.gram_op == "e4m3")
+        return fl(X @ Z, sched.acc)
+
     if sched.gram_op == "e4m3":
         amax_h = np.max(np.maximum(np.abs(H.real), np.abs(H.imag)), axis=(-2, -1), keepdims=True)
         sh = pow2_scale(amax_h)
@@ -222,18 +329,30 @@ def gram(H, Y, sigma2, sched: Schedule = FP64):
         Hq = fl(H * sh, "e4m3")
         Yq = fl(Y * sy, "e4m3")
         Hh = np.conj(np.swapaxes(Hq, -1, -2))
-        G = fl(Hh @ Hq, sched.acc) / (sh * sh)
-        B = fl(Hh @ Yq, sched.acc) / (sh * sy)
+        G = prod(Hh, Hq) / (sh * sh)
+        B = prod(Hh, Yq) / (sh * sy)
     else:
         Hq = fl(H, sched.gram_op)
         Yq = fl(Y, sched.gram_op)
         Hh = np.conj(np.swapaxes(Hq, -1, -2))
-        G = fl(Hh @ Hq, sched.acc)
-        B = fl(Hh @ Yq, sched.acc)
+        G = prod(Hh, Hq)
+        B = prod(Hh, Yq)
+    if sched.accum == "sequential":
+        G = _hermitian_from_upper(G)
     A = G.copy()
     d = np.arange(K)
     A[:, d, d] = fl(G[:, d, d] + fl(s2[:, :, 0] + 0j, sched.work), sched.work)
     return A, B
+
+
+def _hermitian_from_upper(G):
+    """Upper triangle kept, lower = its conjugate transpose, real diagonal."""
+    K = G.shape[-1]
+    up = np.triu(np.ones((K, K), dtype=bool), 1)
+    out = np.where(up, G, np.conj(np.swapaxes(G, -1, -2)))
+    d = np.arange(K)
+    out[..., d, d] = np.real(G[..., d, d])
+    return out
 
 
 def lmmse(A, B):

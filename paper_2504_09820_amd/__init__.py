@@ -1,0 +1,297 @@
+"""MI355X (gfx950) finite-precision block-Jacobi CG massive-MIMO detector.
+
+A thin ctypes binding of the C ABI in include/fpcg.h (libfpcg.so, built by
+``paper_2504_09820_amd.build``).  It only marshals arguments: every step of
+the detector runs in the library's HIP kernels.  PyTorch is used for device
+memory and streams.  If the library is missing the calls raise; there is no
+CPU fallback.
+
+    ctx = Context()
+    xhat, labels, flags = detect(H, Y, sigma2, qam=64, iters=16, schedule="bf16")
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+__all__ = [
+    "FMT", "FLAGS", "Schedule", "schedule", "Context", "FpcgError", "lib", "library_path",
+    "detect", "check", "slice_qam", "round_operand", "select_precision", "Server",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libfpcg.so")
+
+FMT = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "fp8": 4, "e4m3": 4}
+FMT_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16", 4: "fp8"}
+FLAGS = {"nonfinite": 1, "breakdown": 2, "block_not_pd": 4, "fp8_sat": 8}
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5
+
+
+class FpcgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fpcg status {status}: {msg}")
+        self.status = status
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [
+        ("gram_op", ctypes.c_int32), ("mv_op", ctypes.c_int32), ("ip", ctypes.c_int32), ("work", ctypes.c_int32),
+        ("refresh_every", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("variant", ctypes.c_int32),
+    ]
+
+
+def schedule(name: str = "fp64", refresh_every: int = 0, refine_steps: int = 0, variant: int = 0) -> Schedule:
+    """Named schedule: operands of the Gram and of A p in ``name``; u_IP = u_W =
+    FP64 for "fp64", FP32 otherwise."""
+    f = FMT[name]
+    w = 0 if f == 0 else 1
+    return Schedule(f, f, w, w, refresh_every, refine_steps, variant)
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [
+        ("B", ctypes.c_int64), ("Nbs", ctypes.c_int32), ("K", ctypes.c_int32), ("R", ctypes.c_int32),
+        ("io_c64", ctypes.c_int32), ("qam_order", ctypes.c_int32), ("iters", ctypes.c_int32),
+        ("block_L", ctypes.c_int32), ("sched", Schedule),
+        ("H", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("sigma2", ctypes.c_void_p),
+        ("xhat", ctypes.c_void_p), ("labels", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfpcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise FpcgError(E_DEVICE, f"{library_path} is not built; run `python -m paper_2504_09820_amd.build`")
+    L = ctypes.CDLL(library_path)
+    st = ctypes.c_int32
+    vp = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.fpcg_create.argtypes = [i32, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.fpcg_create.restype = st
+    L.fpcg_destroy.argtypes = [vp]
+    L.fpcg_destroy.restype = None
+    L.fpcg_strerror.argtypes = [i32]
+    L.fpcg_strerror.restype = ctypes.c_char_p
+    L.fpcg_last_error.argtypes = []
+    L.fpcg_last_error.restype = ctypes.c_char_p
+    L.fpcg_check.argtypes = [i64, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Schedule)]
+    L.fpcg_check.restype = st
+    L.fpcg_detect.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule), vp, vp, vp]
+    L.fpcg_detect.restype = st
+    L.fpcg_slice.argtypes = [vp, i64, vp, i32, i32, vp]
+    L.fpcg_slice.restype = st
+    L.fpcg_round.argtypes = [vp, i64, vp, i32, ctypes.c_float, vp]
+    L.fpcg_round.restype = st
+    L.fpcg_select_precision.argtypes = [i32, ctypes.c_double, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.fpcg_select_precision.restype = st
+    L.fpcg_server_create.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
+    L.fpcg_server_create.restype = st
+    L.fpcg_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.fpcg_submit.restype = st
+    L.fpcg_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32)]
+    L.fpcg_poll.restype = st
+    L.fpcg_drain.argtypes = [vp]
+    L.fpcg_drain.restype = st
+    L.fpcg_server_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
+    L.fpcg_server_stats.restype = st
+    L.fpcg_server_destroy.argtypes = [vp]
+    L.fpcg_server_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        raise FpcgError(status, lib().fpcg_last_error().decode() or lib().fpcg_strerror(status).decode())
+
+
+def check(B, Nbs, K, R, qam, iters, L=0, sched: Optional[Schedule] = None) -> int:
+    """Host-only validation; returns the status code (0 = accepted)."""
+    return lib().fpcg_check(B, Nbs, K, R, qam, iters, L, ctypes.byref(sched) if sched is not None else None)
+
+
+def select_precision(N: int, kappa: float, allow_fp8: bool = True):
+    """eq. heuristic: returns (format name, u bound)."""
+    f = ctypes.c_int32()
+    u = ctypes.c_double()
+    _check(lib().fpcg_select_precision(N, kappa, 1 if allow_fp8 else 0, ctypes.byref(f), ctypes.byref(u)))
+    return FMT_NAME[f.value], u.value
+
+
+class Context:
+    """A device context (fpcg_create / fpcg_destroy)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().fpcg_create(device, hbm_budget, ctypes.byref(self._h)))
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().fpcg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def _ctx_for(device: int) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _stream_handle(stream, device):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Schedule" = "fp64",
+           refresh_every: int = 0, refine_steps: int = 0, variant: int = 0,
+           ctx: Optional[Context] = None, stream=None, out=None):
+    """Run the detector on device tensors.
+
+    H (B, Nbs, K) and Y (B, Nbs, R): complex64 or complex128 CUDA tensors,
+    contiguous, same dtype; sigma2 (B,) float64 CUDA tensor.  Returns
+    (xhat (B, K, R) like H, labels (B, K, R) uint8, flags (B,) int32 bits).
+    """
+    import torch
+
+    if isinstance(schedule_, str):
+        sched = schedule(schedule_, refresh_every, refine_steps, variant)
+    else:
+        sched = schedule_
+    if H.dtype not in (torch.complex64, torch.complex128) or Y.dtype != H.dtype:
+        raise TypeError("H and Y must both be complex64 or both complex128")
+    if not (H.is_cuda and Y.is_cuda and sigma2.is_cuda):
+        raise TypeError("H, Y and sigma2 must be CUDA tensors")
+    if sigma2.dtype != torch.float64:
+        raise TypeError("sigma2 must be float64")
+    H = H.contiguous()
+    Y = Y.contiguous()
+    sigma2 = sigma2.contiguous()
+    B, Nbs, K = H.shape
+    R = Y.shape[2]
+    if Y.shape[:2] != (B, Nbs) or sigma2.shape != (B,):
+        raise ValueError("shape mismatch between H, Y and sigma2")
+    dev = H.device.index or 0
+    ctx = ctx or _ctx_for(dev)
+    if out is None:
+        xhat = torch.empty((B, K, R), dtype=H.dtype, device=H.device)
+        labels = torch.empty((B, K, R), dtype=torch.uint8, device=H.device)
+        flags = torch.empty((B,), dtype=torch.int32, device=H.device)
+    else:
+        xhat, labels, flags = out
+    _check(lib().fpcg_detect(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
+                             ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                             1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
+                             qam, iters, L, ctypes.byref(sched),
+                             ctypes.c_void_p(xhat.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                             ctypes.c_void_p(flags.data_ptr())))
+    return xhat, labels, flags
+
+
+def slice_qam(x, qam: int, stream=None):
+    """QAM slicer on a complex CUDA tensor; uint8 labels of the same shape."""
+    import torch
+
+    x = x.contiguous()
+    labels = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    _check(lib().fpcg_slice(_stream_handle(stream, x.device), x.numel(), ctypes.c_void_p(x.data_ptr()),
+                            1 if x.dtype == torch.complex64 else 0, qam, ctypes.c_void_p(labels.data_ptr())))
+    return labels
+
+
+def round_operand(x, fmt: str, scale: float = 1.0, stream=None):
+    """fl(.) of the detector's operand conversion on a float32 CUDA tensor."""
+    import torch
+
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    _check(lib().fpcg_round(_stream_handle(stream, x.device), x.numel(), ctypes.c_void_p(x.data_ptr()),
+                            FMT[fmt], scale, ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+class Server:
+    """Continuous-batching request loop over host buffers (fpcg_server_*)."""
+
+    def __init__(self, ctx: Context, n_slots: int = 4, queue_cap: int = 1024):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        _check(lib().fpcg_server_create(ctx.handle, n_slots, queue_cap, ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, H, Y, sigma2, qam, iters, L=0, schedule_: "str | Schedule" = "fp64",
+               refresh_every=0, refine_steps=0, variant=0):
+        """H, Y, sigma2: numpy arrays (complex64/complex128, float64).  Returns a ticket."""
+        import numpy as np
+
+        sched = schedule(schedule_, refresh_every, refine_steps, variant) if isinstance(schedule_, str) else schedule_
+        H = np.ascontiguousarray(H)
+        Y = np.ascontiguousarray(Y, dtype=H.dtype)
+        s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
+        B, Nbs, K = H.shape
+        R = Y.shape[2]
+        xhat = np.empty((B, K, R), dtype=H.dtype)
+        labels = np.empty((B, K, R), dtype=np.uint8)
+        flags = np.empty((B,), dtype=np.uint32)
+        req = _Request(B, Nbs, K, R, 1 if H.dtype == np.complex64 else 0, qam, iters, L, sched,
+                       H.ctypes.data, Y.ctypes.data, s2.ctypes.data, xhat.ctypes.data, labels.ctypes.data,
+                       flags.ctypes.data)
+        t = ctypes.c_uint64()
+        _check(lib().fpcg_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (H, Y, s2, xhat, labels, flags)
+        return t.value
+
+    def poll(self, ticket):
+        """None while running, else (xhat, labels, flags)."""
+        d = ctypes.c_int32()
+        st = lib().fpcg_poll(self._h, ticket, ctypes.byref(d))
+        if st != OK:
+            self._keep.pop(ticket, None)
+            _check(st)
+        if not d.value:
+            return None
+        H, Y, s2, xhat, labels, flags = self._keep.pop(ticket)
+        return xhat, labels, flags
+
+    def drain(self):
+        _check(lib().fpcg_drain(self._h))
+
+    def stats(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().fpcg_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def close(self):
+        if self._h:
+            lib().fpcg_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

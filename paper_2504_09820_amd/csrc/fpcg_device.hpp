@@ -1,0 +1,288 @@
+// Device-side building blocks for gfx950 (CDNA4): matrix-core operand traits
+// per number format, rounding conversions, wave reductions and the QAM slicer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fpcg {
+
+enum Fmt : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3, F8 = 4 };
+
+enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_BREAKDOWN = 2u, FLAG_BLOCK_NOT_PD = 4u, FLAG_FP8_SAT = 8u };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Rounding of an fp32 value to an operand format (round to nearest even).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_bits(float v) {
+    __bf16 h = (__bf16)v;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ uint16_t f16_bits(float v) {
+    _Float16 h = (_Float16)v;
+    return __builtin_bit_cast(uint16_t, h);
+}
+// two fp32 -> two OCP e4m3 bytes (low 16 bits of the result)
+__device__ __forceinline__ uint32_t fp8x2_bits(float a, float b) {
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) {
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+__device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
+    return __builtin_amdgcn_cvt_f32_fp8((int)byte, 0);
+}
+
+// fmt(v): the value v rounded to fmt and widened back to fp32
+__device__ __forceinline__ float round_to(float v, int fmt) {
+    switch (fmt) {
+        case BF16: return bf16_to_f32(bf16_bits(v));
+        case F16: return f16_to_f32(f16_bits(v));
+        case F8: return fp8_to_f32(fp8x2_bits(v, 0.f) & 0xffu);
+        default: return v;
+    }
+}
+
+// Exact power-of-two scale 2^e with 2^e * amax <= 448 < 2^(e+1) * amax
+// (fp8 e4m3 range), e clamped to [-126, 126]; amax <= 0 or not finite -> e = 0.
+__device__ __forceinline__ int fp8_scale_exp(float amax) {
+    if (!(amax > 0.f) || !__builtin_isfinite(amax)) return 0;
+    int ea;
+    float ma = frexpf(amax, &ea);                 // amax = ma 2^ea, ma in [0.5, 1)
+    int e = (ma <= 0.875f) ? (9 - ea) : (8 - ea); // 448 = 0.875 2^9
+    return e < -126 ? -126 : (e > 126 ? 126 : e);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core operand traits.  One 16x16 output tile; lane l holds column
+// l % 16 and four rows crow(l / 16, i), i = 0..3 (4*g + i for the fp32-
+// accumulating shapes, 4*i + g for the f64 shape).  The A and B operands
+// of one instruction carry KPL contraction values per lane; both operands use
+// the same lane/slot -> k assignment, so any consistent packing of the
+// contraction index is valid.
+// ---------------------------------------------------------------------------
+template <int FMT, int KPL> struct Op;
+
+template <> struct Op<F64, 1> {
+    using work = double;
+    using frag = double;
+    using acc = f64x4;
+    // output tile: lane group g, accumulator element i -> row 4*i + g (f64 shape)
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * i + g; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m & 3; i = m >> 2; }
+    static constexpr int KPL = 1;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const work* v, float) { return v[0]; }
+    __device__ static __forceinline__ frag neg(frag a) { return -a; }
+};
+
+template <> struct Op<F32, 1> {
+    using work = float;
+    using frag = float;
+    using acc = f32x4;
+    // output tile: lane group g, accumulator element i -> row crow(g, i); cinv inverts it
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * g + i; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m >> 2; i = m & 3; }
+    static constexpr int KPL = 1;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const work* v, float) { return v[0]; }
+    __device__ static __forceinline__ frag neg(frag a) { return -a; }
+};
+
+template <> struct Op<BF16, 8> {
+    using work = float;
+    using frag = u32x4;
+    using acc = f32x4;
+    // output tile: lane group g, accumulator element i -> row crow(g, i); cinv inverts it
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * g + i; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m >> 2; i = m & 3; }
+    static constexpr int KPL = 8;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const float* v, float s) {
+        frag r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = (uint32_t)bf16_bits(v[2 * j] * s) | ((uint32_t)bf16_bits(v[2 * j + 1] * s) << 16);
+        return r;
+    }
+    __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
+};
+
+template <> struct Op<BF16, 4> {
+    using work = float;
+    using frag = u32x2;
+    using acc = f32x4;
+    // output tile: lane group g, accumulator element i -> row crow(g, i); cinv inverts it
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * g + i; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m >> 2; i = m & 3; }
+    static constexpr int KPL = 4;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(i16x4, a), __builtin_bit_cast(i16x4, b), c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const float* v, float s) {
+        frag r;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) r[j] = (uint32_t)bf16_bits(v[2 * j] * s) | ((uint32_t)bf16_bits(v[2 * j + 1] * s) << 16);
+        return r;
+    }
+    __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
+};
+
+template <> struct Op<F16, 8> {
+    using work = float;
+    using frag = u32x4;
+    using acc = f32x4;
+    // output tile: lane group g, accumulator element i -> row crow(g, i); cinv inverts it
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * g + i; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m >> 2; i = m & 3; }
+    static constexpr int KPL = 8;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const float* v, float s) {
+        frag r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = (uint32_t)f16_bits(v[2 * j] * s) | ((uint32_t)f16_bits(v[2 * j + 1] * s) << 16);
+        return r;
+    }
+    __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
+};
+
+template <> struct Op<F16, 4> {
+    using work = float;
+    using frag = u32x2;
+    using acc = f32x4;
+    // output tile: lane group g, accumulator element i -> row crow(g, i); cinv inverts it
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * g + i; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m >> 2; i = m & 3; }
+    static constexpr int KPL = 4;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(f16x4, a), __builtin_bit_cast(f16x4, b), c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const float* v, float s) {
+        frag r;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) r[j] = (uint32_t)f16_bits(v[2 * j] * s) | ((uint32_t)f16_bits(v[2 * j + 1] * s) << 16);
+        return r;
+    }
+    __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
+};
+
+template <> struct Op<F8, 8> {
+    using work = float;
+    using frag = u32x2;
+    using acc = f32x4;
+    // output tile: lane group g, accumulator element i -> row crow(g, i); cinv inverts it
+    __device__ static __forceinline__ int crow(int g, int i) { return 4 * g + i; }
+    __device__ static __forceinline__ void cinv(int m, int& g, int& i) { g = m >> 2; i = m & 3; }
+    static constexpr int KPL = 8;
+    __device__ static __forceinline__ acc mfma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag pack(const float* v, float s) {
+        frag r;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            r[j] = fp8x2_bits(v[4 * j] * s, v[4 * j + 1] * s) | (fp8x2_bits(v[4 * j + 2] * s, v[4 * j + 3] * s) << 16);
+        return r;
+    }
+    __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80808080u; }
+};
+
+// ---------------------------------------------------------------------------
+// Column reductions over the four 16-lane groups of a wave.  Lanes l, l^16,
+// l^32, l^48 end with bitwise identical results (IEEE addition commutes).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T col_sum(T v) {
+    v = v + __shfl_xor(v, 16);
+    v = v + __shfl_xor(v, 32);
+    return v;
+}
+template <typename T> __device__ __forceinline__ T col_max(T v) {
+    T o = __shfl_xor(v, 16);
+    v = v > o ? v : o;
+    o = __shfl_xor(v, 32);
+    return v > o ? v : o;
+}
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        T o = __shfl_xor(v, s);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// QAM slicer: per axis j = clamp(floor((v nu + m) / 2), 0, m - 1), each
+// operation rounded (no contraction), decided in the precision of T.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+
+template <typename T> __device__ __forceinline__ int slice_axis(T v, T nu, T mm, int m) {
+    T t = add_rn(mul_rn(v, nu), mm);
+    T j = floor(t * T(0.5));
+    if (!__builtin_isfinite(j)) return 0;
+    if (j < T(0)) return 0;
+    if (j > T(m - 1)) return m - 1;
+    return (int)j;
+}
+
+template <typename T> __device__ __forceinline__ uint8_t slice_label(T re, T im, T nu, T mm, int m, int bits) {
+    int ji = slice_axis(re, nu, mm, m);
+    int jq = slice_axis(im, nu, mm, m);
+    return (uint8_t)((((ji ^ (ji >> 1))) << bits) | (jq ^ (jq >> 1)));
+}
+
+// complex element loads/stores for complex64 (float) or complex128 (double) I/O
+template <typename IOT> struct Cx;
+template <> struct Cx<float> {
+    __device__ static __forceinline__ void load(const void* base, int64_t idx, double& re, double& im) {
+        float2 v = reinterpret_cast<const float2*>(base)[idx];
+        re = v.x; im = v.y;
+    }
+    __device__ static __forceinline__ void load(const void* base, int64_t idx, float& re, float& im) {
+        float2 v = reinterpret_cast<const float2*>(base)[idx];
+        re = v.x; im = v.y;
+    }
+    template <typename T> __device__ static __forceinline__ void store(void* base, int64_t idx, T re, T im) {
+        reinterpret_cast<float2*>(base)[idx] = make_float2((float)re, (float)im);
+    }
+};
+template <> struct Cx<double> {
+    __device__ static __forceinline__ void load(const void* base, int64_t idx, double& re, double& im) {
+        double2 v = reinterpret_cast<const double2*>(base)[idx];
+        re = v.x; im = v.y;
+    }
+    // narrowing load for fp32-path schedules: round to fp32 first (the operand
+    // formats are reached from fp32, as the conversion instructions are)
+    __device__ static __forceinline__ void load(const void* base, int64_t idx, float& re, float& im) {
+        double2 v = reinterpret_cast<const double2*>(base)[idx];
+        re = (float)v.x; im = (float)v.y;
+    }
+    template <typename T> __device__ static __forceinline__ void store(void* base, int64_t idx, T re, T im) {
+        reinterpret_cast<double2*>(base)[idx] = make_double2((double)re, (double)im);
+    }
+};
+
+}  // namespace fpcg

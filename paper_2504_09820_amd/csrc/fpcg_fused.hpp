@@ -1,0 +1,865 @@
+// The fused detector kernel for gfx950.
+//
+// One workgroup of NW waves handles one channel and one block of up to 16
+// received vectors (RHS).  Everything between the input read and the output
+// write stays on chip:
+//
+//   1. Gram and matched filter (Sec. II, eq. inversion): A = H^H H + sigma^2 I
+//      and B = H^H Y on the matrix cores, split into real planes:
+//        Re A = Hr^T Hr + Hi^T Hi,  Im A = Hr^T Hi - Hi^T Hr,
+//        Re B = Hr^T Yr + Hi^T Yi,  Im B = Hr^T Yi - Hi^T Yr.
+//      Only the upper triangle of 16x16 complex tiles is formed; the lower
+//      one is its conjugate transpose.  A and B land in LDS in u_W.
+//   2. Block-Jacobi setup (eq. pre_BJ): every L x L diagonal block is
+//      Cholesky-factored and inverted explicitly, M_i = C^{-H} C^{-1}, one
+//      lane per block row.
+//   3. (P)CG (Alg. 2 / Alg. 3): the iterate vectors live in registers.  Lane
+//      (g, n) of wave w owns column n and the SH complex entries
+//      (g*NW + w)*SH + e, e < SH, so Jacobi blocks (L | SH) are lane-local.
+//      A p runs on the matrix cores with the u_MV operands held in registers
+//      (contraction index packed in the lane's own slot order, so the output
+//      tile of one iteration is the input operand of the next without any
+//      data movement); inner products are lane-local FMA chains reduced over
+//      the four lane groups with cross-lane shuffles.
+//   4. Optional FP64 residual refresh r = b - A x on the stored Gram, and FP64
+//      iterative refinement through H (r = H^H (y - H x) - sigma^2 x).
+//   5. QAM slicer epilogue and the x_hat / label stores.
+#pragma once
+
+#include "fpcg_device.hpp"
+
+namespace fpcg {
+
+struct FusedParams {
+    const void* H;
+    const void* Y;
+    const double* sigma2;
+    void* xhat;
+    uint8_t* labels;
+    uint32_t* flags;
+    int64_t B;
+    int32_t Nbs, K, R;
+    int32_t qam, iters;
+    int32_t refresh_every, refine_steps, variant;
+    double nu;     // sqrt(2 (Q - 1) / 3)
+    int32_t m, bits;
+};
+
+template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
+    static constexpr int KP = KP_, NW = NW_, FMT = FMT_, LB = LB_;
+    static constexpr bool LOWP = (FMT != F64 && FMT != F32);
+    static constexpr int SH = KP / (4 * NW);          // complex entries per lane group and wave
+    static constexpr int NF = SH / 4;                 // 16-row output tiles per wave (Re or Im)
+    static constexpr int KPL = LOWP ? (SH % 8 == 0 ? 8 : 4) : 1;
+    static constexpr int NKB = SH / KPL;              // contraction blocks per source wave
+    static constexpr int F = KP / 16;                 // complex 16-column fragments of H
+    static constexpr int KPLG = LOWP ? 8 : 1;         // Gram contraction values per lane
+    static constexpr int KBG = 4 * KPLG;              // antennas per Gram contraction block
+    using O = Op<FMT, KPL>;
+    using OG = Op<FMT, KPLG>;
+    using Wt = typename O::work;
+    static constexpr int NAV = NF * NW * NKB * 2;     // u_MV A-operand fragments per lane
+    static constexpr bool AREG = LOWP || (NAV * (int)sizeof(Wt) <= 256);
+    static constexpr int NPAIR = F * (F + 1) / 2;
+    static constexpr int PPW = (NPAIR + NW - 1) / NW;
+    static constexpr int MFPW = (F + NW - 1) / NW;
+    static constexpr int LDA = KP + 1;
+    static constexpr int RC = 16;                     // antennas per refinement chunk
+    // LDS layout in bytes
+    static constexpr size_t W = sizeof(Wt);
+    static constexpr size_t off_Ar = 0;
+    static constexpr size_t off_Ai = off_Ar + W * KP * LDA;
+    static constexpr size_t off_Br = off_Ai + W * KP * LDA;
+    static constexpr size_t off_Bi = off_Br + W * KP * 16;
+    static constexpr size_t off_M = off_Bi + W * KP * 16;
+    static constexpr size_t sz_M = LB ? 2 * W * KP * LB : 0;
+    static constexpr size_t off_S = off_M + sz_M;     // scratch region (BJ factors or exchange)
+    static constexpr size_t sz_bj = LB ? 4 * W * KP * LB : 0;
+    static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * 8 : 0;    // P / x exchange (doubles)
+    static constexpr size_t sz_red = (size_t)2 * NW * 16 * 4 * 8;                    // dot partials, 2 parities
+    static constexpr size_t sz_ref = (NW > 1) ? (size_t)NW * RC * 16 * 2 * 8 : 0;   // refinement partials
+    static constexpr size_t sz_ex = sz_xp + sz_red + sz_ref;
+    static constexpr size_t sz_S = sz_bj > sz_ex ? sz_bj : sz_ex;
+    static constexpr size_t lds_bytes = off_S + sz_S;
+};
+
+template <int KP, int NW, int FMT, int LB, typename IOT>
+__global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
+    using C = Cfg<KP, NW, FMT, LB>;
+    using O = typename C::O;
+    using OG = typename C::OG;
+    using Wt = typename C::Wt;
+    using frag = typename O::frag;
+    using gfrag = typename OG::frag;
+    using acc_t = typename O::acc;
+    constexpr int SH = C::SH, NF = C::NF, NKB = C::NKB, F = C::F, KPL = C::KPL;
+    constexpr int KPLG = C::KPLG, KBG = C::KBG, LDA = C::LDA, PPW = C::PPW, MFPW = C::MFPW;
+    constexpr int NT = 64 * NW;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    Wt* sAr = reinterpret_cast<Wt*>(smem + C::off_Ar);
+    Wt* sAi = reinterpret_cast<Wt*>(smem + C::off_Ai);
+    Wt* sBr = reinterpret_cast<Wt*>(smem + C::off_Br);
+    Wt* sBi = reinterpret_cast<Wt*>(smem + C::off_Bi);
+    Wt* sMr = reinterpret_cast<Wt*>(smem + C::off_M);
+    Wt* sMi = sMr + KP * (LB ? LB : 1);
+    unsigned char* scr = smem + C::off_S;
+    double* sXP = reinterpret_cast<double*>(scr);                       // [NW][64][2*SH]
+    double* sRed = reinterpret_cast<double*>(scr + C::sz_xp);          // [2][NW][16][4]
+    double* sRef = reinterpret_cast<double*>(scr + C::sz_xp + C::sz_red);   // [NW][RC][16][2]
+    __shared__ uint32_t sFlag;
+    __shared__ float sMaxW[NW];
+    __shared__ float sMaxC[NW][16];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int64_t ch = blockIdx.x;
+    const int col = blockIdx.y * 16 + n;
+    const bool colv = col < P.R;
+    const int K = P.K, Nbs = P.Nbs, R = P.R;
+    const int64_t hoff = ch * (int64_t)Nbs * K;
+    const int64_t yoff = ch * (int64_t)Nbs * R;
+    const double s2 = P.sigma2[ch];
+    if (tid == 0) sFlag = 0u;
+    uint32_t myflag = 0u;
+
+    // block-wide max over one float per thread (fixed order, result in all threads)
+    auto block_max = [&](float v) -> float {
+        v = wave_max(v);
+        if constexpr (NW > 1) {
+            __syncthreads();
+            if (lane == 0) sMaxW[wave] = v;
+            __syncthreads();
+            v = sMaxW[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) v = fmaxf(v, sMaxW[w]);
+        }
+        return v;
+    };
+    // max over the lanes of one column, across waves
+    auto column_max = [&](float v) -> float {
+        v = col_max(v);
+        if constexpr (NW > 1) {
+            __syncthreads();
+            if (g == 0) sMaxC[wave][n] = v;
+            __syncthreads();
+            v = sMaxC[0][n];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) v = fmaxf(v, sMaxC[w][n]);
+        }
+        return v;
+    };
+
+    // ------------------------------------------------------------ fp8 scales
+    int eH = 0, eY = 0;
+    if constexpr (FMT == F8) {
+        float mh = 0.f;
+        for (int64_t i = tid; i < (int64_t)Nbs * K; i += NT) {
+            float re, im;
+            Cx<IOT>::load(P.H, hoff + i, re, im);
+            mh = fmaxf(mh, fmaxf(fabsf(re), fabsf(im)));
+        }
+        mh = block_max(mh);
+        float my = 0.f;
+        if (colv) {
+            for (int a = g + 4 * wave; a < Nbs; a += 4 * NW) {
+                float re, im;
+                Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, re, im);
+                my = fmaxf(my, fmaxf(fabsf(re), fabsf(im)));
+            }
+        }
+        my = column_max(my);
+        eH = fp8_scale_exp(mh);
+        eY = fp8_scale_exp(my);
+    }
+    const float sH = ldexpf(1.f, eH), sY = ldexpf(1.f, eY);
+
+    // ------------------------------------------------------------ 1. Gram + matched filter
+    {
+        acc_t gAr[PPW], gAi[PPW], gBr[MFPW], gBi[MFPW];
+#pragma unroll
+        for (int s = 0; s < PPW; ++s) { gAr[s] = acc_t{0, 0, 0, 0}; gAi[s] = acc_t{0, 0, 0, 0}; }
+#pragma unroll
+        for (int s = 0; s < MFPW; ++s) { gBr[s] = acc_t{0, 0, 0, 0}; gBi[s] = acc_t{0, 0, 0, 0}; }
+
+        for (int a0 = 0; a0 < Nbs; a0 += KBG) {
+            Wt hr[F][KPLG], hi[F][KPLG], yr[KPLG], yi[KPLG];
+#pragma unroll
+            for (int j = 0; j < KPLG; ++j) {
+                const int a = a0 + g * KPLG + j;
+                const bool av = a < Nbs;
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int k = 16 * f + n;
+                    hr[f][j] = 0; hi[f][j] = 0;
+                    if (av && k < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + k, hr[f][j], hi[f][j]);
+                }
+                yr[j] = 0; yi[j] = 0;
+                if (av && colv) Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, yr[j], yi[j]);
+            }
+            gfrag Xr[F], Xi[F], nXi[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                Xr[f] = OG::pack(hr[f], sH);
+                Xi[f] = OG::pack(hi[f], sH);
+                nXi[f] = OG::neg(Xi[f]);
+            }
+            const gfrag Yr = OG::pack(yr, sY), Yi = OG::pack(yi, sY);
+            int q = 0;
+#pragma unroll
+            for (int f1 = 0; f1 < F; ++f1) {
+#pragma unroll
+                for (int f2 = f1; f2 < F; ++f2) {
+                    if (NW == 1 || q % NW == wave) {
+                        const int s = q / NW;
+                        gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
+                        gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
+                        gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
+                        gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
+                    }
+                    ++q;
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if (NW == 1 || f % NW == wave) {
+                    const int s = f / NW;
+                    gBr[s] = OG::mfma(Xr[f], Yr, gBr[s]);
+                    gBr[s] = OG::mfma(Xi[f], Yi, gBr[s]);
+                    gBi[s] = OG::mfma(Xr[f], Yi, gBi[s]);
+                    gBi[s] = OG::mfma(nXi[f], Yr, gBi[s]);
+                }
+            }
+        }
+
+        // scale back (fp8), add sigma^2, mirror into LDS
+        const Wt invH = (Wt)ldexpf(1.f, -eH), invY = (Wt)ldexpf(1.f, -eY);
+        const Wt s2w = (Wt)s2;
+        bool bad = false;
+        int q = 0;
+#pragma unroll
+        for (int f1 = 0; f1 < F; ++f1) {
+#pragma unroll
+            for (int f2 = f1; f2 < F; ++f2) {
+                if (NW == 1 || q % NW == wave) {
+                    const int s = q / NW;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int row = 16 * f1 + OG::crow(g, jj), cc = 16 * f2 + n;
+                        Wt ar = (Wt)gAr[s][jj], ai = (Wt)gAi[s][jj];
+                        if constexpr (FMT == F8) { ar = ar * invH * invH; ai = ai * invH * invH; }
+                        if (row == cc) {
+                            ai = 0;
+                            ar = (row < K) ? ar + s2w : (Wt)1;
+                        }
+                        bad |= !__builtin_isfinite(ar) || !__builtin_isfinite(ai);
+                        sAr[row * LDA + cc] = ar;
+                        sAi[row * LDA + cc] = ai;
+                        if (f1 != f2) {
+                            sAr[cc * LDA + row] = ar;
+                            sAi[cc * LDA + row] = -ai;
+                        }
+                    }
+                }
+                ++q;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            if (NW == 1 || f % NW == wave) {
+                const int s = f / NW;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int row = 16 * f + OG::crow(g, jj);
+                    Wt br = (Wt)gBr[s][jj], bi = (Wt)gBi[s][jj];
+                    if constexpr (FMT == F8) { br = br * invH * invY; bi = bi * invH * invY; }
+                    bad |= !__builtin_isfinite(br) || !__builtin_isfinite(bi);
+                    sBr[row * 16 + n] = br;
+                    sBi[row * 16 + n] = bi;
+                }
+            }
+        }
+        if (bad) myflag |= FLAG_NONFINITE;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ fp8 scale of A (u_MV operand)
+    int eA = 0;
+    if constexpr (FMT == F8) {
+        float ma = 0.f;
+        for (int i = tid; i < K * K; i += NT) {
+            const int r = i / K, c = i % K;
+            ma = fmaxf(ma, fmaxf(fabsf((float)sAr[r * LDA + c]), fabsf((float)sAi[r * LDA + c])));
+        }
+        ma = block_max(ma);
+        eA = fp8_scale_exp(ma);
+    }
+    const float sA = ldexpf(1.f, eA);
+
+    // ------------------------------------------------------------ 2. block-Jacobi setup (eq. pre_BJ)
+    if constexpr (LB > 0) {
+        Wt* sLr = reinterpret_cast<Wt*>(scr);
+        Wt* sLi = sLr + KP * LB;
+        Wt* sTr = sLi + KP * LB;
+        Wt* sTi = sTr + KP * LB;
+        const bool act = tid < KP;
+        const int t = act ? tid : 0;
+        const int i = t % LB, cb = t - i;             // row in block, first row of block
+        Wt ar[LB], ai[LB];
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            ar[j] = sAr[(cb + i) * LDA + cb + j];
+            ai[j] = sAi[(cb + i) * LDA + cb + j];
+        }
+        Wt diag = 0;
+#pragma unroll
+        for (int j = 0; j < LB; ++j)
+            if (j == i) diag = ar[j];
+        bool bad = false;
+        // Cholesky A_blk = C C^H, C lower triangular, row i owned by this lane
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            if (act && i == j) {
+                Wt d = ar[j];
+                if (!(d > 0) || !__builtin_isfinite(d)) { bad = true; d = 1; }
+                sLr[(cb + j) * LB + j] = sqrt(d);
+                sLi[(cb + j) * LB + j] = 0;
+            }
+            __syncthreads();
+            const Wt ljj = sLr[(cb + j) * LB + j];
+            Wt lr = 0, li = 0;
+            if (act && i > j) {
+                lr = ar[j] / ljj;
+                li = ai[j] / ljj;
+                sLr[(cb + i) * LB + j] = lr;
+                sLi[(cb + i) * LB + j] = li;
+            }
+            __syncthreads();
+            if (act && i > j) {
+#pragma unroll
+                for (int k = j + 1; k < LB; ++k) {
+                    if (k <= i) {
+                        // a_ik -= l_ij conj(l_kj)
+                        const Wt kr = sLr[(cb + k) * LB + j], ki = sLi[(cb + k) * LB + j];
+                        ar[k] = ar[k] - (lr * kr + li * ki);
+                        ai[k] = ai[k] - (li * kr - lr * ki);
+                    }
+                }
+            }
+        }
+        // block-wide "not PD" decision: any row of the block failed
+        __syncthreads();
+        uint32_t* sBad = reinterpret_cast<uint32_t*>(sTr);   // temporary use before T is written
+        if (act && i == 0) sBad[cb / LB] = 0u;
+        __syncthreads();
+        if (act && bad) atomicOr(&sBad[cb / LB], 1u);
+        __syncthreads();
+        const bool blk_bad = act && sBad[cb / LB] != 0u;
+        __syncthreads();
+        // T = C^{-1}: this lane computes column i of T
+        Wt tr[LB], ti[LB];
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            tr[r] = 0; ti[r] = 0;
+            if (r == i) {
+                tr[r] = (Wt)1 / sLr[(cb + r) * LB + r];
+            } else if (r > i) {
+                Wt sr = 0, si = 0;
+#pragma unroll
+                for (int m = 0; m < r; ++m) {
+                    if (m >= i) {
+                        const Wt cr = sLr[(cb + r) * LB + m], ci = sLi[(cb + r) * LB + m];
+                        sr = sr + (cr * tr[m] - ci * ti[m]);
+                        si = si + (cr * ti[m] + ci * tr[m]);
+                    }
+                }
+                const Wt crr = sLr[(cb + r) * LB + r];
+                tr[r] = -sr / crr;
+                ti[r] = -si / crr;
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                sTr[(cb + r) * LB + i] = tr[r];
+                sTi[(cb + r) * LB + i] = ti[r];
+            }
+        }
+        __syncthreads();
+        // M = T^H T: row i
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                Wt mr = 0, mi = 0;
+#pragma unroll
+                for (int m = 0; m < LB; ++m) {
+                    if (m >= i && m >= j) {
+                        const Wt ar_ = sTr[(cb + m) * LB + i], ai_ = sTi[(cb + m) * LB + i];   // T[m][i]
+                        const Wt br_ = sTr[(cb + m) * LB + j], bi_ = sTi[(cb + m) * LB + j];   // T[m][j]
+                        mr = mr + (ar_ * br_ + ai_ * bi_);
+                        mi = mi + (ar_ * bi_ - ai_ * br_);
+                    }
+                }
+                if (blk_bad) {
+                    mr = 0; mi = 0;
+                    if (j == i) mr = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / diag : (Wt)1;
+                }
+                sMr[(cb + i) * LB + j] = mr;
+                sMi[(cb + i) * LB + j] = mi;
+            }
+            if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
+        }
+        __syncthreads();
+    }
+
+    // ------------------------------------------------------------ u_MV operand of A
+    // A-operand lane (g, n) of output tile phi holds row rowc(phi) (fixed per lane)
+    // and the contraction values of source wave ws, block kb: columns colc(ws, kb, j).
+    auto rowc = [&](int phi) -> int {
+        int gm, im;
+        O::cinv(n, gm, im);
+        return (gm * NW + wave) * SH + 4 * phi + im;
+    };
+    // the same for the f64 shape used by the FP64 residual refresh
+    auto rowc64 = [&](int phi) -> int {
+        int gm, im;
+        Op<F64, 1>::cinv(n, gm, im);
+        return (gm * NW + wave) * SH + 4 * phi + im;
+    };
+    auto colc = [&](int ws, int kb, int j) -> int { return (g * NW + ws) * SH + kb * KPL + j; };
+    frag afr[C::AREG ? NF : 1][C::AREG ? NW : 1][C::AREG ? NKB : 1][2];
+    if constexpr (C::AREG) {
+#pragma unroll
+        for (int phi = 0; phi < NF; ++phi)
+#pragma unroll
+            for (int ws = 0; ws < NW; ++ws)
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    Wt vr[KPL], vi[KPL];
+                    const int rr_ = rowc(phi);
+#pragma unroll
+                    for (int j = 0; j < KPL; ++j) {
+                        vr[j] = sAr[rr_ * LDA + colc(ws, kb, j)];
+                        vi[j] = sAi[rr_ * LDA + colc(ws, kb, j)];
+                    }
+                    afr[phi][ws][kb][0] = O::pack(vr, sA);
+                    afr[phi][ws][kb][1] = O::pack(vi, sA);
+                }
+    }
+    auto A_op = [&](int phi, int ws, int kb, int ri) -> frag {
+        if constexpr (C::AREG) {
+            return afr[phi][ws][kb][ri];
+        } else {
+            const Wt* src = ri ? sAi : sAr;
+            Wt v = src[rowc(phi) * LDA + colc(ws, kb, 0)];
+            return O::pack(&v, 1.f);
+        }
+    };
+
+    // ------------------------------------------------------------ helpers for the solve
+    int parity = 0;
+    // sum of per-lane partials over the column (lane groups, then waves in order);
+    // up to four values at once
+    auto col_reduce = [&](Wt* v, int cnt) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < cnt) v[k] = col_sum(v[k]);
+        if constexpr (NW > 1) {
+            double* red = sRed + parity * NW * 16 * 4;
+            if (g == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < cnt) red[(wave * 16 + n) * 4 + k] = (double)v[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < cnt) {
+                    Wt s = (Wt)red[(0 * 16 + n) * 4 + k];
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) s = s + (Wt)red[(w * 16 + n) * 4 + k];
+                    v[k] = s;
+                }
+            }
+            parity ^= 1;
+        }
+    };
+    // publish this wave's slots of two vectors (NW > 1) so that other waves can read them
+    auto publish = [&](const Wt* vr, const Wt* vi) {
+        if constexpr (NW > 1) {
+            double* dst = sXP + ((size_t)wave * 64 + lane) * 2 * SH;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { dst[e] = (double)vr[e]; dst[SH + e] = (double)vi[e]; }
+        }
+    };
+    auto fetch = [&](int ws, int e, int part) -> Wt {
+        return (Wt)sXP[((size_t)ws * 64 + lane) * 2 * SH + part * SH + e];
+    };
+
+    // z = M r (block-diagonal, lane-local, u_W)
+    auto apply_M = [&](const Wt* rr, const Wt* ri, Wt* zr, Wt* zi) {
+        if constexpr (LB > 0) {
+            const int base = (g * NW + wave) * SH;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                const int j0 = (e / LB) * LB;
+                const int c = base + e;
+                Wt ar = 0, ai = 0;
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    const Wt mr = sMr[c * LB + j], mi = sMi[c * LB + j];
+                    ar = fma(mr, rr[j0 + j], ar);
+                    ar = fma(-mi, ri[j0 + j], ar);
+                    ai = fma(mr, ri[j0 + j], ai);
+                    ai = fma(mi, rr[j0 + j], ai);
+                }
+                zr[e] = ar;
+                zi[e] = ai;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { zr[e] = rr[e]; zi[e] = ri[e]; }
+        }
+    };
+
+    const int base_c = (g * NW + wave) * SH;
+    double x64r[SH], x64i[SH];
+    Wt xr[SH], xi[SH];
+#pragma unroll
+    for (int e = 0; e < SH; ++e) { x64r[e] = 0; x64i[e] = 0; }
+
+    const int passes = 1 + P.refine_steps;
+    int es = 0;                                       // exponent of the current pass's residual scale
+    for (int pass = 0; pass < passes; ++pass) {
+        if (pass > 0) {
+            // -------------------------------------------- FP64 residual through H
+            double resr[SH], resi[SH];
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { resr[e] = 0; resi[e] = 0; }
+            if constexpr (NW == 1) {
+                // one antenna at a time: e_a = y_a - h_a x (column sums), res += conj(h_a) e_a
+#pragma unroll 1
+                for (int a = 0; a < Nbs; ++a) {
+                    double hr[SH], hi[SH];
+                    double sr = 0, si = 0;
+#pragma unroll
+                    for (int e = 0; e < SH; ++e) {
+                        const int c = base_c + e;
+                        hr[e] = 0; hi[e] = 0;
+                        if (c < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + c, hr[e], hi[e]);
+                        sr = fma(hr[e], x64r[e], sr);
+                        sr = fma(-hi[e], x64i[e], sr);
+                        si = fma(hr[e], x64i[e], si);
+                        si = fma(hi[e], x64r[e], si);
+                    }
+                    sr = col_sum(sr);
+                    si = col_sum(si);
+                    double yr = 0, yi = 0;
+                    if (colv) Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, yr, yi);
+                    const double vr = yr - sr, vi = yi - si;
+#pragma unroll
+                    for (int e = 0; e < SH; ++e) {
+                        resr[e] = fma(hr[e], vr, resr[e]);
+                        resr[e] = fma(hi[e], vi, resr[e]);
+                        resi[e] = fma(hr[e], vi, resi[e]);
+                        resi[e] = fma(-hi[e], vr, resi[e]);
+                    }
+                }
+            } else {
+                // chunks of RC antennas: per-wave column partials through LDS
+#pragma unroll 1
+                for (int a0 = 0; a0 < Nbs; a0 += C::RC) {
+#pragma unroll 1
+                    for (int u = 0; u < C::RC; ++u) {
+                        const int a = a0 + u;
+                        double sr = 0, si = 0;
+                        if (a < Nbs) {
+#pragma unroll
+                            for (int e = 0; e < SH; ++e) {
+                                const int c = base_c + e;
+                                double hr = 0, hi = 0;
+                                if (c < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + c, hr, hi);
+                                sr = fma(hr, x64r[e], sr);
+                                sr = fma(-hi, x64i[e], sr);
+                                si = fma(hr, x64i[e], si);
+                                si = fma(hi, x64r[e], si);
+                            }
+                        }
+                        sr = col_sum(sr);
+                        si = col_sum(si);
+                        if (g == 0) {
+                            sRef[((wave * C::RC + u) * 16 + n) * 2 + 0] = sr;
+                            sRef[((wave * C::RC + u) * 16 + n) * 2 + 1] = si;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll 1
+                    for (int u = 0; u < C::RC; ++u) {
+                        const int a = a0 + u;
+                        if (a >= Nbs) break;
+                        double er = sRef[((0 * C::RC + u) * 16 + n) * 2 + 0];
+                        double ei = sRef[((0 * C::RC + u) * 16 + n) * 2 + 1];
+#pragma unroll
+                        for (int w = 1; w < NW; ++w) {
+                            er += sRef[((w * C::RC + u) * 16 + n) * 2 + 0];
+                            ei += sRef[((w * C::RC + u) * 16 + n) * 2 + 1];
+                        }
+                        double yr = 0, yi = 0;
+                        if (colv) Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, yr, yi);
+                        const double vr = yr - er, vi = yi - ei;
+#pragma unroll
+                        for (int e = 0; e < SH; ++e) {
+                            const int c = base_c + e;
+                            double hr = 0, hi = 0;
+                            if (c < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + c, hr, hi);
+                            resr[e] = fma(hr, vr, resr[e]);
+                            resr[e] = fma(hi, vi, resr[e]);
+                            resi[e] = fma(hr, vi, resi[e]);
+                            resi[e] = fma(-hi, vr, resi[e]);
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            double cm = 0;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                resr[e] = fma(-s2, x64r[e], resr[e]);
+                resi[e] = fma(-s2, x64i[e], resi[e]);
+                if (base_c + e >= K || !colv) { resr[e] = 0; resi[e] = 0; }
+                cm = fmax(cm, fmax(fabs(resr[e]), fabs(resi[e])));
+            }
+            // per-column power-of-two scale: max |r| lands in [1, 2)
+            cm = col_max(cm);
+            if constexpr (NW > 1) {
+                __syncthreads();
+                if (g == 0) sRef[wave * 16 + n] = cm;
+                __syncthreads();
+                double mm = sRef[n];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) mm = fmax(mm, sRef[w * 16 + n]);
+                cm = mm;
+                __syncthreads();
+            }
+            es = 0;
+            if (cm > 0 && __builtin_isfinite(cm)) {
+                int ex;
+                frexp(cm, &ex);
+                es = ex - 1;
+                es = es < -126 ? -126 : (es > 126 ? 126 : es);
+            }
+            const double sc = ldexp(1.0, -es);
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                const int c = base_c + e;
+                sBr[c * 16 + n] = (Wt)(resr[e] * sc);
+                sBi[c * 16 + n] = (Wt)(resi[e] * sc);
+            }
+            __syncthreads();
+        }
+
+        // ------------------------------------------------ 3. (P)CG
+        Wt rr[SH], ri[SH], pr[SH], pi[SH], wr[SH], wi[SH], zr[SH], zi[SH];
+#pragma unroll
+        for (int e = 0; e < SH; ++e) {
+            xr[e] = 0; xi[e] = 0;
+            rr[e] = sBr[(base_c + e) * 16 + n];
+            ri[e] = sBi[(base_c + e) * 16 + n];
+        }
+        apply_M(rr, ri, pr, pi);                       // p0 = M r0 (Alg. 3) or r0 (Alg. 2)
+        Wt rho_cur;
+        {
+            Wt v[4];
+            v[0] = 0;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { v[0] = fma(rr[e], pr[e], v[0]); v[0] = fma(ri[e], pi[e], v[0]); }
+            col_reduce(v, 1);
+            rho_cur = v[0];                            // r0^H r0 (Alg. 2) / r0^H z0 (textbook PCG)
+        }
+        bool live = true, broken = false;
+        int eP = 0;
+        for (int it = 1; it <= P.iters; ++it) {
+            // ---- varpi = A p   [u_MV]
+            if constexpr (NW > 1) {
+                __syncthreads();
+                publish(pr, pi);
+                __syncthreads();
+            }
+            if constexpr (FMT == F8) {
+                float am = 0.f;
+#pragma unroll
+                for (int e = 0; e < SH; ++e) am = fmaxf(am, fmaxf(fabsf(pr[e]), fabsf(pi[e])));
+                eP = fp8_scale_exp(column_max(am));
+            }
+            const float sP = ldexpf(1.f, eP);
+            acc_t Wr_[NF], Wi_[NF];
+#pragma unroll
+            for (int phi = 0; phi < NF; ++phi) { Wr_[phi] = acc_t{0, 0, 0, 0}; Wi_[phi] = acc_t{0, 0, 0, 0}; }
+#pragma unroll
+            for (int ws = 0; ws < NW; ++ws) {
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    Wt vr[KPL], vi[KPL];
+#pragma unroll
+                    for (int j = 0; j < KPL; ++j) {
+                        const int e = kb * KPL + j;
+                        if (NW == 1 || ws == wave) { vr[j] = pr[e]; vi[j] = pi[e]; }
+                        else { vr[j] = fetch(ws, e, 0); vi[j] = fetch(ws, e, 1); }
+                    }
+                    const frag Br = O::pack(vr, sP), Bi = O::pack(vi, sP), nBi = O::neg(Bi);
+#pragma unroll
+                    for (int phi = 0; phi < NF; ++phi) {
+                        const frag a_r = A_op(phi, ws, kb, 0), a_i = A_op(phi, ws, kb, 1);
+                        Wr_[phi] = O::mfma(a_r, Br, Wr_[phi]);
+                        Wr_[phi] = O::mfma(a_i, nBi, Wr_[phi]);
+                        Wi_[phi] = O::mfma(a_i, Br, Wi_[phi]);
+                        Wi_[phi] = O::mfma(a_r, Bi, Wi_[phi]);
+                    }
+                }
+            }
+            const Wt inv_s = (Wt)(ldexpf(1.f, -eA)), inv_p = (Wt)(ldexpf(1.f, -eP));
+#pragma unroll
+            for (int phi = 0; phi < NF; ++phi)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    Wt a = (Wt)Wr_[phi][jj], b = (Wt)Wi_[phi][jj];
+                    if constexpr (FMT == F8) { a = a * inv_s * inv_p; b = b * inv_s * inv_p; }
+                    wr[4 * phi + jj] = a;
+                    wi[4 * phi + jj] = b;
+                }
+            // ---- phi = p^H varpi, rho_{i-1}  [u_IP]
+            Wt v[4];
+            v[0] = 0; v[1] = 0;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                v[0] = fma(pr[e], wr[e], v[0]);
+                v[0] = fma(pi[e], wi[e], v[0]);
+                v[1] = fma(rr[e], pr[e], v[1]);
+                v[1] = fma(ri[e], pi[e], v[1]);
+            }
+            const bool need_rp = (LB > 0) && (P.variant == 0);
+            col_reduce(v, need_rp ? 2 : 1);
+            const Wt ph = v[0];
+            const Wt rho_prev = need_rp ? v[1] : rho_cur;
+            // ---- guard, alpha, x and r updates  [u_W]
+            const bool ok = live && __builtin_isfinite(ph) && __builtin_isfinite(rho_prev) && ph > 0 && rho_prev > 0;
+            if (live && !ok && colv) broken = true;
+            live = ok;
+            if (live) {
+                const Wt alpha = rho_prev / ph;
+#pragma unroll
+                for (int e = 0; e < SH; ++e) {
+                    xr[e] = fma(alpha, pr[e], xr[e]);
+                    xi[e] = fma(alpha, pi[e], xi[e]);
+                    rr[e] = fma(-alpha, wr[e], rr[e]);
+                    ri[e] = fma(-alpha, wi[e], ri[e]);
+                }
+            }
+            // ---- FP64 residual refresh on the stored Gram
+            if (P.refresh_every > 0 && it % P.refresh_every == 0 && it < P.iters) {
+                if constexpr (NW > 1) {
+                    __syncthreads();
+                    publish(xr, xi);
+                    __syncthreads();
+                }
+                f64x4 Rr[NF], Ri[NF];
+#pragma unroll
+                for (int phi = 0; phi < NF; ++phi) { Rr[phi] = f64x4{0, 0, 0, 0}; Ri[phi] = f64x4{0, 0, 0, 0}; }
+#pragma unroll
+                for (int ws = 0; ws < NW; ++ws) {
+#pragma unroll
+                    for (int kb = 0; kb < SH; ++kb) {
+                        double bx, by;
+                        if (NW == 1 || ws == wave) { bx = (double)xr[kb]; by = (double)xi[kb]; }
+                        else { bx = (double)fetch(ws, kb, 0); by = (double)fetch(ws, kb, 1); }
+                        const int cc = (g * NW + ws) * SH + kb;
+#pragma unroll
+                        for (int phi = 0; phi < NF; ++phi) {
+                            const double a_r = (double)sAr[rowc64(phi) * LDA + cc];
+                            const double a_i = (double)sAi[rowc64(phi) * LDA + cc];
+                            Rr[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, bx, Rr[phi], 0, 0, 0);
+                            Rr[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i, by, Rr[phi], 0, 0, 0);
+                            Ri[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, bx, Ri[phi], 0, 0, 0);
+                            Ri[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, by, Ri[phi], 0, 0, 0);
+                        }
+                    }
+                }
+                if (live) {
+#pragma unroll
+                    for (int phi = 0; phi < NF; ++phi)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const int e = 4 * phi + jj;
+                            const double b_r = (double)sBr[(base_c + e) * 16 + n];
+                            const double b_i = (double)sBi[(base_c + e) * 16 + n];
+                            rr[e] = (Wt)(b_r - Rr[phi][jj]);
+                            ri[e] = (Wt)(b_i - Ri[phi][jj]);
+                        }
+                }
+            }
+            // ---- z = M r, rho_i, beta, p
+            apply_M(rr, ri, zr, zi);
+            v[0] = 0;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { v[0] = fma(rr[e], zr[e], v[0]); v[0] = fma(ri[e], zi[e], v[0]); }
+            col_reduce(v, 1);
+            const Wt rho_new = v[0];
+            if (live) {
+                const Wt beta = rho_new / rho_prev;
+#pragma unroll
+                for (int e = 0; e < SH; ++e) {
+                    pr[e] = fma(beta, pr[e], zr[e]);
+                    pi[e] = fma(beta, pi[e], zi[e]);
+                }
+            }
+            rho_cur = rho_new;
+        }
+        if (broken) myflag |= FLAG_BREAKDOWN;
+        if (pass == 0) {
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { x64r[e] = (double)xr[e]; x64i[e] = (double)xi[e]; }
+        } else {
+            const double us = ldexp(1.0, es);          // x += d / sc, exact scaling
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                x64r[e] = x64r[e] + (double)xr[e] * us;
+                x64i[e] = x64i[e] + (double)xi[e] * us;
+            }
+        }
+    }
+
+    // ------------------------------------------------------------ 5. slicer + stores
+    if (colv) {
+        if (P.refine_steps > 0) {
+            const double nu = P.nu, mm = (double)P.m;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                const int c = base_c + e;
+                if (c < K) {
+                    const int64_t o = (ch * K + c) * (int64_t)R + col;
+                    Cx<IOT>::store(P.xhat, o, x64r[e], x64i[e]);
+                    P.labels[o] = slice_label<double>(x64r[e], x64i[e], nu, mm, P.m, P.bits);
+                }
+            }
+        } else {
+            const Wt nu = (Wt)P.nu, mm = (Wt)P.m;
+#pragma unroll
+            for (int e = 0; e < SH; ++e) {
+                const int c = base_c + e;
+                if (c < K) {
+                    const int64_t o = (ch * K + c) * (int64_t)R + col;
+                    Cx<IOT>::store(P.xhat, o, xr[e], xi[e]);
+                    P.labels[o] = slice_label<Wt>(xr[e], xi[e], nu, mm, P.m, P.bits);
+                }
+            }
+        }
+    }
+    if (myflag) atomicOr(&sFlag, myflag);
+    __syncthreads();
+    if (tid == 0 && P.flags) {
+        if (gridDim.y == 1) P.flags[ch] = sFlag;           // the only workgroup of this channel
+        else if (sFlag) atomicOr(&P.flags[ch], sFlag);     // flags were cleared before the launch
+    }
+}
+
+}  // namespace fpcg

@@ -1,0 +1,298 @@
+// Host runtime behind include/fpcg.h: argument validation, variant dispatch,
+// the stand-alone slicer / rounding kernels, the precision heuristic, error
+// reporting and contexts.  The serving queue lives in fpcg_serve.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fpcg.h"
+#include "fpcg_host.hpp"
+#include "fpcg_registry.hpp"
+
+namespace fpcg {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+fpcg_status fail(fpcg_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ------------------------------------------------------------------ variant table
+static std::vector<KernelEntry>& table() {
+    static std::vector<KernelEntry> t;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        register_f64(t);
+        register_f32(t);
+        register_bf16(t);
+        register_f16(t);
+        register_f8(t);
+    });
+    return t;
+}
+
+static const KernelEntry* find_entry(int KP, int FMT, int LB, int io_c64) {
+    for (const auto& e : table())
+        if (e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64) return &e;
+    return nullptr;
+}
+
+// smallest padded K with a compiled variant for (K, fmt, L)
+static int pick_kp(int K, int FMT, int L) {
+    static const int kps[] = {16, 32, 64};
+    for (int kp : kps) {
+        if (kp < K) continue;
+        const int sh = kp / (4 * waves_for(kp));
+        if (L > sh) continue;
+        if (FMT == F8 && kp < 32) continue;
+        if (!find_entry(kp, FMT, L, 1)) continue;
+        return kp;
+    }
+    return 0;
+}
+
+static bool valid_fmt(int f) { return f >= FPCG_F64 && f <= FPCG_F8E4M3; }
+
+fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam, int32_t iters,
+                       int32_t L, const fpcg_schedule* s, Plan* plan) {
+    fpcg_schedule def = {FPCG_F64, FPCG_F64, FPCG_F64, FPCG_F64, 0, 0, 0};
+    if (!s) s = &def;
+    if (B < 0 || B > 0x7fffffffLL) return fail(FPCG_E_INVAL, "B=%lld out of range [0, 2^31-1]", (long long)B);
+    if (Nbs < 1) return fail(FPCG_E_INVAL, "Nbs=%d must be >= 1", Nbs);
+    if (K < 1) return fail(FPCG_E_INVAL, "K=%d must be >= 1", K);
+    if (R < 1) return fail(FPCG_E_INVAL, "R=%d must be >= 1", R);
+    if (!(qam == 4 || qam == 16 || qam == 64 || qam == 256))
+        return fail(FPCG_E_INVAL, "qam_order=%d must be 4, 16, 64 or 256", qam);
+    if (iters < 0) return fail(FPCG_E_INVAL, "iters=%d must be >= 0", iters);
+    if (L < 0) return fail(FPCG_E_INVAL, "block_L=%d must be >= 0", L);
+    if (L > 0 && K % L != 0) return fail(FPCG_E_INVAL, "block_L=%d does not divide K=%d", L, K);
+    if (!valid_fmt(s->gram_op) || !valid_fmt(s->mv_op) || !valid_fmt(s->ip) || !valid_fmt(s->work))
+        return fail(FPCG_E_INVAL, "schedule format out of range");
+    if (s->refresh_every < 0) return fail(FPCG_E_INVAL, "refresh_every=%d must be >= 0", s->refresh_every);
+    if (s->refine_steps < 0 || s->refine_steps > 16)
+        return fail(FPCG_E_INVAL, "refine_steps=%d must be in [0, 16]", s->refine_steps);
+    if (s->variant != 0 && s->variant != 1) return fail(FPCG_E_INVAL, "variant=%d must be 0 or 1", s->variant);
+    if (s->gram_op != s->mv_op)
+        return fail(FPCG_E_UNSUPPORTED, "gram_op (%d) must equal mv_op (%d)", s->gram_op, s->mv_op);
+    const int want_work = s->mv_op == FPCG_F64 ? FPCG_F64 : FPCG_F32;
+    if (s->work != want_work || s->ip != want_work)
+        return fail(FPCG_E_UNSUPPORTED, "work and ip must be %s for mv_op %d", want_work == FPCG_F64 ? "F64" : "F32", s->mv_op);
+    if (K > 64) return fail(FPCG_E_UNSUPPORTED, "K=%d > 64 is not built", K);
+    if (L != 0 && L != 4 && L != 8) return fail(FPCG_E_UNSUPPORTED, "block_L=%d not built (0, 4, 8)", L);
+    // map the public format enum to the kernel enum (identical values)
+    const int fmt = s->mv_op;
+    const int kp = pick_kp(K, fmt, L);
+    if (!kp) return fail(FPCG_E_UNSUPPORTED, "no variant for K=%d fmt=%d L=%d", K, fmt, L);
+    if (plan) {
+        plan->KP = kp;
+        plan->FMT = fmt;
+        plan->LB = L;
+        plan->sched = *s;
+    }
+    return FPCG_OK;
+}
+
+struct ScopedDevice {
+    int prev = -1;
+    explicit ScopedDevice(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~ScopedDevice() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+__global__ void zero_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+static inline unsigned grid_for(int64_t n, int threads) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65535) b = 65535;
+    return (unsigned)b;
+}
+
+fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                          const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,
+                          int32_t iters, void* xhat, uint8_t* labels, uint32_t* flags) {
+    const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
+    if (!e) return fail(FPCG_E_UNSUPPORTED, "variant missing");
+    if (B == 0) return FPCG_OK;
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        for (const auto& t : table())
+            if (t.lds > 65536) (void)hipFuncSetAttribute(t.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.lds);
+    });
+    (void)device;
+    if (flags && R > 16) {   // several workgroups per channel OR their flags together
+        hipLaunchKernelGGL(zero_u32, dim3(grid_for(B, 256)), dim3(256), 0, stream, flags, B);
+    }
+    FusedParams p;
+    p.H = H; p.Y = Y; p.sigma2 = sigma2; p.xhat = xhat; p.labels = labels; p.flags = flags;
+    p.B = B; p.Nbs = Nbs; p.K = K; p.R = R; p.qam = qam; p.iters = iters;
+    p.refresh_every = plan.sched.refresh_every;
+    p.refine_steps = plan.sched.refine_steps;
+    p.variant = plan.sched.variant;
+    p.m = (int)std::lround(std::sqrt((double)qam));
+    p.bits = 0;
+    while ((1 << p.bits) < p.m) ++p.bits;
+    p.nu = std::sqrt(2.0 * (qam - 1) / 3.0);
+    dim3 grid((unsigned)B, (unsigned)((R + 15) / 16));
+    e->launch(p, grid, stream);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(FPCG_E_DEVICE, "fused kernel launch: %s", hipGetErrorString(err));
+    return FPCG_OK;
+}
+
+// ------------------------------------------------------------------ slicer / rounding kernels
+template <typename T>
+__global__ void slice_kernel(int64_t n, const T* x, int m, int bits, double nu_d, uint8_t* labels) {
+    const T nu = (T)nu_d, mm = (T)m;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        labels[i] = slice_label<T>(x[2 * i], x[2 * i + 1], nu, mm, m, bits);
+}
+
+__global__ void round_kernel(int64_t n, const float* in, int fmt, float scale, float inv, float* out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = round_to(in[i] * scale, fmt) * inv;
+}
+
+}  // namespace fpcg
+
+using namespace fpcg;
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* fpcg_strerror(int32_t status) {
+    switch (status) {
+        case FPCG_OK: return "ok";
+        case FPCG_E_INVAL: return "invalid argument";
+        case FPCG_E_NOMEM: return "device memory budget exceeded";
+        case FPCG_E_DEVICE: return "HIP runtime error";
+        case FPCG_E_UNSUPPORTED: return "configuration not built";
+        case FPCG_E_BUSY: return "queue full";
+        default: return "unknown status";
+    }
+}
+
+const char* fpcg_last_error(void) { return g_last_error.c_str(); }
+
+fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out) {
+    clear_error();
+    if (!out) return fail(FPCG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(FPCG_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= count) return fail(FPCG_E_INVAL, "device %d not in [0, %d)", device, count);
+    ScopedDevice sd(device);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(FPCG_E_DEVICE, "hipMemGetInfo failed");
+    fpcg_ctx* c = new fpcg_ctx();
+    c->device = device;
+    c->budget = hbm_budget ? hbm_budget : (size_t)(0.8 * (double)free_b);
+    (void)table();
+    *out = c;
+    return FPCG_OK;
+}
+
+void fpcg_destroy(fpcg_ctx* ctx) { delete ctx; }
+
+fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam_order, int32_t iters,
+                       int32_t block_L, const fpcg_schedule* sched) {
+    clear_error();
+    return check_args(B, Nbs, K, R, qam_order, iters, block_L, sched, nullptr);
+}
+
+fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
+                        const void* Y, int32_t io_c64, const double* sigma2, int32_t qam_order, int32_t iters,
+                        int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags) {
+    clear_error();
+    if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    Plan plan;
+    fpcg_status st = check_args(B, Nbs, K, R, qam_order, iters, block_L, sched, &plan);
+    if (st != FPCG_OK) return st;
+    if (B > 0 && (!H || !Y || !sigma2 || !xhat || !labels))
+        return fail(FPCG_E_INVAL, "H, Y, sigma2, xhat and labels must be non-NULL");
+    ScopedDevice sd(ctx->device);
+    return launch_detect(ctx->device, (hipStream_t)stream, plan, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters,
+                         xhat, labels, flags);
+}
+
+fpcg_status fpcg_slice(void* stream, int64_t n, const void* x, int32_t x_c64, int32_t qam_order, uint8_t* labels) {
+    clear_error();
+    if (n < 0) return fail(FPCG_E_INVAL, "n=%lld < 0", (long long)n);
+    if (!(qam_order == 4 || qam_order == 16 || qam_order == 64 || qam_order == 256))
+        return fail(FPCG_E_INVAL, "qam_order=%d", qam_order);
+    if (n == 0) return FPCG_OK;
+    if (!x || !labels) return fail(FPCG_E_INVAL, "NULL pointer");
+    const int m = (int)std::lround(std::sqrt((double)qam_order));
+    int bits = 0;
+    while ((1 << bits) < m) ++bits;
+    const double nu = std::sqrt(2.0 * (qam_order - 1) / 3.0);
+    hipStream_t s = (hipStream_t)stream;
+    if (x_c64)
+        hipLaunchKernelGGL(slice_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const float*)x, m, bits, nu, labels);
+    else
+        hipLaunchKernelGGL(slice_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const double*)x, m, bits, nu, labels);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(FPCG_E_DEVICE, "slice launch: %s", hipGetErrorString(err));
+    return FPCG_OK;
+}
+
+fpcg_status fpcg_round(void* stream, int64_t n, const float* in, int32_t fmt, float scale, float* out) {
+    clear_error();
+    if (n < 0) return fail(FPCG_E_INVAL, "n < 0");
+    if (fmt != FPCG_F32 && fmt != FPCG_BF16 && fmt != FPCG_F16 && fmt != FPCG_F8E4M3)
+        return fail(FPCG_E_INVAL, "fmt=%d must be F32, BF16, F16 or F8E4M3", fmt);
+    int ex = 0;
+    if (!(scale > 0.f) || std::frexp(scale, &ex) != 0.5f) return fail(FPCG_E_INVAL, "scale must be a power of two");
+    if (n == 0) return FPCG_OK;
+    if (!in || !out) return fail(FPCG_E_INVAL, "NULL pointer");
+    hipLaunchKernelGGL(round_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, n, in, fmt, scale, 1.0f / scale, out);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(FPCG_E_DEVICE, "round launch: %s", hipGetErrorString(err));
+    return FPCG_OK;
+}
+
+fpcg_status fpcg_select_precision(int32_t N, double kappa, int32_t allow_fp8, int32_t* fmt, double* u_bound) {
+    clear_error();
+    if (N < 1 || !(kappa >= 1.0) || !std::isfinite(kappa)) return fail(FPCG_E_INVAL, "need N >= 1 and finite kappa >= 1");
+    if (!fmt) return fail(FPCG_E_INVAL, "fmt is NULL");
+    const double bound = 1.0 / (std::pow((double)N, 1.5) * std::sqrt(kappa));
+    if (u_bound) *u_bound = bound;
+    // cheapest first; fp16 before bf16 (same matrix-core rate, 3 more significand bits)
+    struct Cand { int fmt; double u; };
+    const Cand cands[] = {{FPCG_F8E4M3, std::ldexp(1.0, -4)},
+                          {FPCG_F16, std::ldexp(1.0, -11)},
+                          {FPCG_BF16, std::ldexp(1.0, -8)},
+                          {FPCG_F32, std::ldexp(1.0, -24)},
+                          {FPCG_F64, std::ldexp(1.0, -53)}};
+    for (const Cand& c : cands) {
+        if (c.fmt == FPCG_F8E4M3 && !allow_fp8) continue;
+        if (c.u < bound) { *fmt = c.fmt; return FPCG_OK; }
+    }
+    *fmt = FPCG_F64;
+    return FPCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,33 @@
+// Internal host-side declarations shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fpcg.h"
+
+struct fpcg_ctx {
+    int device = 0;
+    size_t budget = 0;
+};
+
+namespace fpcg {
+
+struct Plan {
+    int KP = 0, FMT = 0, LB = 0;
+    fpcg_schedule sched{};
+};
+
+fpcg_status fail(fpcg_status st, const char* fmt, ...);
+void clear_error();
+
+fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam, int32_t iters, int32_t L,
+                       const fpcg_schedule* s, Plan* plan);
+
+fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K,
+                          int32_t R, const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,
+                          int32_t iters, void* xhat, uint8_t* labels, uint32_t* flags);
+
+}  // namespace fpcg

@@ -1,0 +1,264 @@
+// Continuous-batching request loop (fpcg_server_* in fpcg.h).
+//
+// Requests carry host buffers.  A request is admitted when a stream slot is
+// free and its device footprint fits the context's budget next to the
+// requests already in flight; its inputs are staged through pinned memory,
+// the detector runs on the slot's stream and the outputs come back through
+// pinned memory.  Requests arriving while others run are admitted as slots
+// and memory free up, so work of different requests overlaps on the device.
+// Each channel is computed by its own workgroup in a fixed order, so a
+// request's results do not depend on what else is in flight.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "fpcg_host.hpp"
+
+using namespace fpcg;
+
+namespace {
+
+struct Req {
+    uint64_t ticket = 0;
+    fpcg_request r{};
+    Plan plan;
+    size_t in_bytes = 0, out_bytes = 0, bytes = 0;
+    int state = 0;  // 0 queued, 1 running, 2 done
+    fpcg_status status = FPCG_OK;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Req* req = nullptr;
+    void* dbuf = nullptr;   // device: H | Y | sigma2 | xhat | labels | flags
+    size_t dcap = 0;
+    void* hbuf = nullptr;   // pinned staging, same layout
+    size_t hcap = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t h, y, s2, x, lab, fl, total;
+};
+
+Layout layout_of(const fpcg_request& r) {
+    const size_t el = r.io_c64 ? 8 : 16;
+    Layout L;
+    size_t o = 0;
+    L.h = o; o = align256(o + (size_t)r.B * r.Nbs * r.K * el);
+    L.y = o; o = align256(o + (size_t)r.B * r.Nbs * r.R * el);
+    L.s2 = o; o = align256(o + (size_t)r.B * 8);
+    L.x = o; o = align256(o + (size_t)r.B * r.K * r.R * el);
+    L.lab = o; o = align256(o + (size_t)r.B * r.K * r.R);
+    L.fl = o; o = align256(o + (size_t)r.B * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct fpcg_server {
+    fpcg_ctx* ctx = nullptr;
+    int cap = 0;
+    std::vector<Slot> slots;
+    std::deque<Req*> queue;
+    std::unordered_map<uint64_t, Req*> reqs;
+    size_t held = 0;   // device bytes of the slot buffers in use
+    uint64_t next = 1;
+    std::mutex mu;
+};
+
+static fpcg_status retire_and_admit(fpcg_server* s) {
+    // retire finished requests
+    for (Slot& sl : s->slots) {
+        if (!sl.req) continue;
+        hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) continue;
+        Req* rq = sl.req;
+        if (q != hipSuccess) {
+            rq->status = fail(FPCG_E_DEVICE, "request %llu: %s", (unsigned long long)rq->ticket, hipGetErrorString(q));
+        } else {
+            const Layout L = layout_of(rq->r);
+            const char* hb = static_cast<const char*>(sl.hbuf);
+            const size_t el = rq->r.io_c64 ? 8 : 16;
+            std::memcpy(rq->r.xhat, hb + L.x, (size_t)rq->r.B * rq->r.K * rq->r.R * el);
+            std::memcpy(rq->r.labels, hb + L.lab, (size_t)rq->r.B * rq->r.K * rq->r.R);
+            if (rq->r.flags) std::memcpy(rq->r.flags, hb + L.fl, (size_t)rq->r.B * 4);
+        }
+        rq->state = 2;
+        s->held -= rq->bytes;
+        sl.req = nullptr;
+    }
+    // admit in arrival order while a slot is free and the budget allows
+    while (!s->queue.empty()) {
+        Req* rq = s->queue.front();
+        if (s->held + rq->bytes > s->ctx->budget) break;
+        Slot* free_slot = nullptr;
+        for (Slot& sl : s->slots)
+            if (!sl.req) { free_slot = &sl; break; }
+        if (!free_slot) break;
+        s->queue.pop_front();
+        Slot& sl = *free_slot;
+        const Layout L = layout_of(rq->r);
+        if (sl.dcap < L.total) {
+            if (sl.dbuf) (void)hipFree(sl.dbuf);
+            if (sl.hbuf) (void)hipHostFree(sl.hbuf);
+            sl.dbuf = nullptr; sl.hbuf = nullptr; sl.dcap = sl.hcap = 0;
+            if (hipMalloc(&sl.dbuf, L.total) != hipSuccess || hipHostMalloc(&sl.hbuf, L.total, hipHostMallocDefault) != hipSuccess) {
+                rq->status = fail(FPCG_E_NOMEM, "device/pinned allocation of %zu bytes failed", L.total);
+                rq->state = 2;
+                continue;
+            }
+            sl.dcap = sl.hcap = L.total;
+        }
+        char* hb = static_cast<char*>(sl.hbuf);
+        char* db = static_cast<char*>(sl.dbuf);
+        const fpcg_request& r = rq->r;
+        const size_t el = r.io_c64 ? 8 : 16;
+        const size_t nh = (size_t)r.B * r.Nbs * r.K * el, ny = (size_t)r.B * r.Nbs * r.R * el;
+        std::memcpy(hb + L.h, r.H, nh);
+        std::memcpy(hb + L.y, r.Y, ny);
+        std::memcpy(hb + L.s2, r.sigma2, (size_t)r.B * 8);
+        hipError_t e = hipMemcpyAsync(db, hb, L.x, hipMemcpyHostToDevice, sl.stream);
+        fpcg_status st = FPCG_OK;
+        if (e != hipSuccess) st = fail(FPCG_E_DEVICE, "H2D copy: %s", hipGetErrorString(e));
+        if (st == FPCG_OK)
+            st = launch_detect(s->ctx->device, sl.stream, rq->plan, r.B, r.Nbs, r.K, r.R, db + L.h, db + L.y, r.io_c64,
+                               reinterpret_cast<const double*>(db + L.s2), r.qam_order, r.iters, db + L.x,
+                               reinterpret_cast<uint8_t*>(db + L.lab), reinterpret_cast<uint32_t*>(db + L.fl));
+        if (st == FPCG_OK) {
+            e = hipMemcpyAsync(hb + L.x, db + L.x, L.total - L.x, hipMemcpyDeviceToHost, sl.stream);
+            if (e != hipSuccess) st = fail(FPCG_E_DEVICE, "D2H copy: %s", hipGetErrorString(e));
+        }
+        if (st == FPCG_OK) {
+            e = hipEventRecord(sl.done, sl.stream);
+            if (e != hipSuccess) st = fail(FPCG_E_DEVICE, "event record: %s", hipGetErrorString(e));
+        }
+        if (st != FPCG_OK) {
+            rq->status = st;
+            rq->state = 2;
+            (void)hipStreamSynchronize(sl.stream);
+            continue;
+        }
+        rq->state = 1;
+        sl.req = rq;
+        s->held += rq->bytes;
+    }
+    return FPCG_OK;
+}
+
+extern "C" {
+
+fpcg_status fpcg_server_create(fpcg_ctx* ctx, int32_t n_slots, int32_t queue_cap, fpcg_server** out) {
+    clear_error();
+    if (!ctx || !out) return fail(FPCG_E_INVAL, "NULL argument");
+    if (n_slots < 1 || n_slots > 16) return fail(FPCG_E_INVAL, "n_slots=%d must be in [1, 16]", n_slots);
+    if (queue_cap < 1) return fail(FPCG_E_INVAL, "queue_cap=%d must be >= 1", queue_cap);
+    (void)hipSetDevice(ctx->device);
+    fpcg_server* s = new fpcg_server();
+    s->ctx = ctx;
+    s->cap = queue_cap;
+    s->slots.resize(n_slots);
+    for (Slot& sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            fpcg_server_destroy(s);
+            return fail(FPCG_E_DEVICE, "stream/event creation failed");
+        }
+    }
+    *out = s;
+    return FPCG_OK;
+}
+
+fpcg_status fpcg_submit(fpcg_server* s, const fpcg_request* req, uint64_t* ticket) {
+    clear_error();
+    if (!s || !req || !ticket) return fail(FPCG_E_INVAL, "NULL argument");
+    Plan plan;
+    fpcg_status st = check_args(req->B, req->Nbs, req->K, req->R, req->qam_order, req->iters, req->block_L, &req->sched, &plan);
+    if (st != FPCG_OK) return st;
+    if (req->B > 0 && (!req->H || !req->Y || !req->sigma2 || !req->xhat || !req->labels))
+        return fail(FPCG_E_INVAL, "request buffers must be non-NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const size_t bytes = layout_of(*req).total;
+    if (bytes > s->ctx->budget) return fail(FPCG_E_NOMEM, "request needs %zu bytes, budget %zu", bytes, s->ctx->budget);
+    if ((int)s->queue.size() >= s->cap) return fail(FPCG_E_BUSY, "queue full (%d)", s->cap);
+    Req* rq = new Req();
+    rq->ticket = s->next++;
+    rq->r = *req;
+    rq->plan = plan;
+    rq->bytes = bytes;
+    s->reqs[rq->ticket] = rq;
+    s->queue.push_back(rq);
+    *ticket = rq->ticket;
+    (void)hipSetDevice(s->ctx->device);
+    return retire_and_admit(s);
+}
+
+fpcg_status fpcg_poll(fpcg_server* s, uint64_t ticket, int32_t* done) {
+    clear_error();
+    if (!s || !done) return fail(FPCG_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    (void)hipSetDevice(s->ctx->device);
+    retire_and_admit(s);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(FPCG_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Req* rq = it->second;
+    *done = rq->state == 2 ? 1 : 0;
+    if (rq->state == 2) {
+        fpcg_status st = rq->status;
+        s->reqs.erase(it);
+        delete rq;
+        return st;
+    }
+    return FPCG_OK;
+}
+
+fpcg_status fpcg_drain(fpcg_server* s) {
+    clear_error();
+    if (!s) return fail(FPCG_E_INVAL, "NULL server");
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            (void)hipSetDevice(s->ctx->device);
+            retire_and_admit(s);
+            bool busy = !s->queue.empty();
+            for (Slot& sl : s->slots) busy |= sl.req != nullptr;
+            if (!busy) return FPCG_OK;
+            for (Slot& sl : s->slots)
+                if (sl.req) { (void)hipEventSynchronize(sl.done); break; }
+        }
+    }
+}
+
+fpcg_status fpcg_server_stats(fpcg_server* s, int32_t* in_flight, int32_t* queued, size_t* bytes_held) {
+    clear_error();
+    if (!s) return fail(FPCG_E_INVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int f = 0;
+    for (Slot& sl : s->slots) f += sl.req != nullptr;
+    if (in_flight) *in_flight = f;
+    if (queued) *queued = (int32_t)s->queue.size();
+    if (bytes_held) *bytes_held = s->held;
+    return FPCG_OK;
+}
+
+void fpcg_server_destroy(fpcg_server* s) {
+    if (!s) return;
+    (void)fpcg_drain(s);
+    for (Slot& sl : s->slots) {
+        if (sl.dbuf) (void)hipFree(sl.dbuf);
+        if (sl.hbuf) (void)hipHostFree(sl.hbuf);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    for (auto& kv : s->reqs) delete kv.second;
+    delete s;
+}
+
+}  // extern "C"

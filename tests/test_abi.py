@@ -1,0 +1,116 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function declared in include/fpcg.h, validates arguments on the host exactly
+as documented, and its precision heuristic agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="session")
+def fp():
+    import paper_2504_09820_amd as fp
+
+    if not os.path.exists(fp.library_path):
+        from paper_2504_09820_amd import build
+
+        build.build(incremental=True, verbose=False)
+    fp.lib()
+    return fp
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fpcg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpcg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(fp):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(fp.lib(), n), n
+
+
+def test_strerror_codes(fp):
+    L = fp.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.fpcg_strerror(code).decode()
+    assert L.fpcg_strerror(-99).decode() == "unknown status"
+
+
+def test_check_accepts_built_configurations(fp):
+    for name in ("fp64", "fp32", "bf16", "fp16", "fp8"):
+        s = fp.schedule(name)
+        assert fp.check(1000, 64, 8, 1, 16, 8, 0, s) == 0 or name == "fp8"
+        assert fp.check(16384, 128, 32, 14, 64, 16, 0, s) == 0
+        assert fp.check(8192, 256, 64, 14, 64, 16, 8, s) == 0
+        assert fp.check(10, 256, 64, 14, 64, 16, 4, fp.schedule(name, refresh_every=4)) == 0
+    assert fp.check(0, 1, 1, 1, 4, 0, 0, None) == 0          # empty batch, FP64 default
+    assert fp.check(3, 1, 1, 1, 4, 1, 0, fp.schedule("fp64")) == 0
+    assert fp.check(3, 50, 20, 17, 16, 5, 4, fp.schedule("fp32", refine_steps=2)) == 0
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 64, 8, 1, 16, 8, 0), -1),
+    ((2**31, 64, 8, 1, 16, 8, 0), -1),
+    ((10, 0, 8, 1, 16, 8, 0), -1),
+    ((10, 64, 0, 1, 16, 8, 0), -1),
+    ((10, 64, 8, 0, 16, 8, 0), -1),
+    ((10, 64, 8, 1, 8, 8, 0), -1),      # not a square QAM order
+    ((10, 64, 8, 1, 16, -1, 0), -1),
+    ((10, 64, 8, 1, 16, 8, 3), -1),     # L does not divide K
+    ((10, 64, 8, 1, 16, 8, -4), -1),
+    ((10, 256, 128, 1, 16, 8, 0), -4),  # K > 64 not built
+    ((10, 64, 32, 1, 16, 8, 16), -4),   # L = 16 not built
+    ((10, 64, 16, 1, 16, 8, 2), -4),    # L = 2 not built
+])
+def test_check_rejects(fp, args, code):
+    assert fp.check(*args, fp.schedule("fp32")) == code
+
+
+def test_check_rejects_bad_schedules(fp):
+    S = fp.Schedule
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(9, 9, 1, 1, 0, 0, 0)) == -1
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, -1, 0, 0)) == -1
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, 0, 99, 0)) == -1
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, 0, 0, 2)) == -1
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 2, 1, 1, 0, 0, 0)) == -4   # gram_op != mv_op
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(2, 2, 0, 0, 0, 0, 0)) == -4   # FP64 work with bf16 operands
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(0, 0, 1, 1, 0, 0, 0)) == -4   # FP32 work with FP64 operands
+
+
+def test_last_error_message(fp):
+    assert fp.check(10, 64, 8, 1, 16, 8, 3, fp.schedule("fp32")) == -1
+    assert "divide" in fp.lib().fpcg_last_error().decode()
+
+
+def test_select_precision_matches_oracle_heuristic(fp):
+    from oracle import theory as T
+
+    for N in (8, 16, 32, 64, 100, 128):
+        for kappa in (1.0, 2.0, 5.0, 17.25, 50.0, 245.0, 1e3, 1e5, 1e9):
+            for allow in (True, False):
+                name, u = fp.select_precision(N, kappa, allow)
+                ref = T.select_format(N, kappa, allow_fp8=allow)
+                assert {"fp8": "e4m3"}.get(name, name) == ref, (N, kappa, allow)
+                assert u == pytest.approx(T.heuristic_bound(N, kappa), rel=1e-14)
+
+
+def test_select_precision_rejects(fp):
+    f = ctypes.c_int32()
+    assert fp.lib().fpcg_select_precision(0, 10.0, 1, ctypes.byref(f), None) == -1
+    assert fp.lib().fpcg_select_precision(8, 0.5, 1, ctypes.byref(f), None) == -1
+    assert fp.lib().fpcg_select_precision(8, float("nan"), 1, ctypes.byref(f), None) == -1
+
+
+def test_no_cpu_fallback_without_device(fp):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(fp.FpcgError):
+        fp.Context(0)

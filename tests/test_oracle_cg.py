@@ -490,3 +490,37 @@ def test_bit_errors_brute_force():
     a = rng.integers(0, 256, 1000)
     b = rng.integers(0, 256, 1000)
     assert D.bit_errors(a, b) == sum(bin(int(x) ^ int(y)).count("1") for x, y in zip(a, b))
+
+
+# ---------------------------------------------------------------- sequential accumulation order
+def test_sequential_matvec_is_an_ordered_fma_chain():
+    """accum='sequential': each output is the fp32 fused multiply-add chain over k."""
+    rng = np.random.default_rng(8)
+    n = 5
+    A = (rng.standard_normal((1, n, n)) + 1j * rng.standard_normal((1, n, n))).astype(np.complex64).astype(np.complex128)
+    p = (rng.standard_normal((1, n, 2)) + 1j * rng.standard_normal((1, n, 2))).astype(np.complex64).astype(np.complex128)
+    w = D.MatVec(A, D.schedule("bf16", accum="sequential"))(p)
+    f32 = lambda v: float(np.float32(v))
+    for i in range(n):
+        for c in range(2):
+            wr = wi = 0.0
+            for k in range(n):
+                ar, ai = _bf16(A[0, i, k].real), _bf16(A[0, i, k].imag)
+                pr, pi = _bf16(p[0, k, c].real), _bf16(p[0, k, c].imag)
+                wr = f32(ar * pr + wr)
+                wr = f32(-ai * pi + wr)
+                wi = f32(ai * pr + wi)
+                wi = f32(ar * pi + wi)
+            assert w[0, i, c].real == wr and w[0, i, c].imag == wi
+
+
+def test_sequential_order_agrees_with_exact_order_when_well_conditioned():
+    wl = small_wl(B=4, Nbs=64, K=16, R=2, zeta=0.0)
+    r1 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.FP64)
+    r2 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.schedule("fp64", accum="sequential"))
+    assert np.linalg.norm(r1.xhat - r2.xhat) / np.linalg.norm(r1.xhat) < 1e-13
+    r3 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.FP32)
+    r4 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.schedule("fp32", accum="sequential"))
+    assert 0 < np.linalg.norm(r3.xhat - r4.xhat) / np.linalg.norm(r3.xhat) < 1e-5
+    A, _ = D.gram(wl.H, wl.Y, wl.sigma2, D.schedule("fp32", accum="sequential"))
+    assert np.array_equal(A, np.conj(np.swapaxes(A, -1, -2)))
