@@ -254,6 +254,44 @@ template <typename T> __device__ __forceinline__ uint8_t slice_label(T re, T im,
     return (uint8_t)((((ji ^ (ji >> 1))) << bits) | (jq ^ (jq >> 1)));
 }
 
+// ---------------------------------------------------------------------------
+// Range-checked loads through a buffer resource covering [base, base+bytes):
+// a byte offset outside that range reads as zero in hardware, so masked
+// loads need no branch and every load of a block can be in flight at once.
+// ---------------------------------------------------------------------------
+typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+constexpr uint32_t OOB = 0x80000000u;   // any offset >= the range reads 0
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ Buf(const void* base, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
+};
+
+template <typename IOT> struct CxB;
+// (vector elements are copied to scalars before a bit cast: a bit cast applied
+// directly to an ext-vector element reads the vector's first element)
+template <> struct CxB<float> {
+    static constexpr uint32_t bytes = 8;
+    template <typename T> __device__ static __forceinline__ void load(const Buf& b, uint32_t off, T& re, T& im) {
+        const u32x2v v = __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, 0);
+        const uint32_t lo = v[0], hi = v[1];
+        re = (T)__uint_as_float(lo);
+        im = (T)__uint_as_float(hi);
+    }
+};
+template <> struct CxB<double> {
+    static constexpr uint32_t bytes = 16;
+    template <typename T> __device__ static __forceinline__ void load(const Buf& b, uint32_t off, T& re, T& im) {
+        const u32x4v v = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, 0);
+        const uint64_t a = ((uint64_t)(uint32_t)v[1] << 32) | (uint32_t)v[0];
+        const uint64_t c = ((uint64_t)(uint32_t)v[3] << 32) | (uint32_t)v[2];
+        re = (T)__longlong_as_double((long long)a);
+        im = (T)__longlong_as_double((long long)c);
+    }
+};
+
 // complex element loads/stores for complex64 (float) or complex128 (double) I/O
 template <typename IOT> struct Cx;
 template <> struct Cx<float> {

@@ -119,6 +119,11 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     const int K = P.K, Nbs = P.Nbs, R = P.R;
     const int64_t hoff = ch * (int64_t)Nbs * K;
     const int64_t yoff = ch * (int64_t)Nbs * R;
+    constexpr uint32_t ES = CxB<IOT>::bytes;
+    const Buf bH(static_cast<const char*>(P.H) + hoff * ES, (uint32_t)Nbs * K * ES);   // this channel's H
+    const Buf bY(static_cast<const char*>(P.Y) + yoff * ES, (uint32_t)Nbs * R * ES);   // this channel's Y
+    auto hofs = [&](int a, int k) -> uint32_t { return (a < Nbs && k < K) ? ((uint32_t)a * K + k) * ES : OOB; };
+    auto yofs = [&](int a) -> uint32_t { return (a < Nbs && colv) ? ((uint32_t)a * R + col) * ES : OOB; };
     const double s2 = P.sigma2[ch];
     if (tid == 0) sFlag = 0u;
     uint32_t myflag = 0u;
@@ -154,19 +159,17 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     int eH = 0, eY = 0;
     if constexpr (FMT == F8) {
         float mh = 0.f;
-        for (int64_t i = tid; i < (int64_t)Nbs * K; i += NT) {
+        for (int i = tid; i < Nbs * K; i += NT) {
             float re, im;
-            Cx<IOT>::load(P.H, hoff + i, re, im);
+            CxB<IOT>::load(bH, (uint32_t)i * ES, re, im);
             mh = fmaxf(mh, fmaxf(fabsf(re), fabsf(im)));
         }
         mh = block_max(mh);
         float my = 0.f;
-        if (colv) {
-            for (int a = g + 4 * wave; a < Nbs; a += 4 * NW) {
-                float re, im;
-                Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, re, im);
-                my = fmaxf(my, fmaxf(fabsf(re), fabsf(im)));
-            }
+        for (int a = g + 4 * wave; a < Nbs; a += 4 * NW) {
+            float re, im;
+            CxB<IOT>::load(bY, yofs(a), re, im);
+            my = fmaxf(my, fmaxf(fabsf(re), fabsf(im)));
         }
         my = column_max(my);
         eH = fp8_scale_exp(mh);
@@ -183,19 +186,14 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
         for (int s = 0; s < MFPW; ++s) { gBr[s] = acc_t{0, 0, 0, 0}; gBi[s] = acc_t{0, 0, 0, 0}; }
 
         for (int a0 = 0; a0 < Nbs; a0 += KBG) {
+            // range-checked loads (padding reads zero): all loads of the block in flight together
             Wt hr[F][KPLG], hi[F][KPLG], yr[KPLG], yi[KPLG];
 #pragma unroll
             for (int j = 0; j < KPLG; ++j) {
                 const int a = a0 + g * KPLG + j;
-                const bool av = a < Nbs;
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    const int k = 16 * f + n;
-                    hr[f][j] = 0; hi[f][j] = 0;
-                    if (av && k < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + k, hr[f][j], hi[f][j]);
-                }
-                yr[j] = 0; yi[j] = 0;
-                if (av && colv) Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, yr[j], yi[j]);
+                for (int f = 0; f < F; ++f) CxB<IOT>::load(bH, hofs(a, 16 * f + n), hr[f][j], hi[f][j]);
+                CxB<IOT>::load(bY, yofs(a), yr[j], yi[j]);
             }
             gfrag Xr[F], Xi[F], nXi[F];
 #pragma unroll
@@ -545,8 +543,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
 #pragma unroll
                     for (int e = 0; e < SH; ++e) {
                         const int c = base_c + e;
-                        hr[e] = 0; hi[e] = 0;
-                        if (c < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + c, hr[e], hi[e]);
+                        CxB<IOT>::load(bH, hofs(a, c), hr[e], hi[e]);
                         sr = fma(hr[e], x64r[e], sr);
                         sr = fma(-hi[e], x64i[e], sr);
                         si = fma(hr[e], x64i[e], si);
@@ -554,8 +551,8 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                     }
                     sr = col_sum(sr);
                     si = col_sum(si);
-                    double yr = 0, yi = 0;
-                    if (colv) Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, yr, yi);
+                    double yr, yi;
+                    CxB<IOT>::load(bY, yofs(a), yr, yi);
                     const double vr = yr - sr, vi = yi - si;
 #pragma unroll
                     for (int e = 0; e < SH; ++e) {
@@ -577,8 +574,8 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
 #pragma unroll
                             for (int e = 0; e < SH; ++e) {
                                 const int c = base_c + e;
-                                double hr = 0, hi = 0;
-                                if (c < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + c, hr, hi);
+                                double hr, hi;
+                                CxB<IOT>::load(bH, hofs(a, c), hr, hi);
                                 sr = fma(hr, x64r[e], sr);
                                 sr = fma(-hi, x64i[e], sr);
                                 si = fma(hr, x64i[e], si);
@@ -604,14 +601,14 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                             er += sRef[((w * C::RC + u) * 16 + n) * 2 + 0];
                             ei += sRef[((w * C::RC + u) * 16 + n) * 2 + 1];
                         }
-                        double yr = 0, yi = 0;
-                        if (colv) Cx<IOT>::load(P.Y, yoff + (int64_t)a * R + col, yr, yi);
+                        double yr, yi;
+                        CxB<IOT>::load(bY, yofs(a), yr, yi);
                         const double vr = yr - er, vi = yi - ei;
 #pragma unroll
                         for (int e = 0; e < SH; ++e) {
                             const int c = base_c + e;
-                            double hr = 0, hi = 0;
-                            if (c < K) Cx<IOT>::load(P.H, hoff + (int64_t)a * K + c, hr, hi);
+                            double hr, hi;
+                            CxB<IOT>::load(bH, hofs(a, c), hr, hi);
                             resr[e] = fma(hr, vr, resr[e]);
                             resr[e] = fma(hi, vi, resr[e]);
                             resi[e] = fma(hr, vi, resi[e]);
