@@ -75,7 +75,13 @@ enum {
  *             on the stored Gram (0 = off)
  *   refine_steps  : FP64 iterative refinement steps: r = H^H (y - H x) -
  *             sigma^2 x in FP64, solve A d = r with the same schedule, x += d
- *   variant : 0 = Alg. 3 as printed (rho = r^H p); 1 = textbook PCG (r^H z)
+ *   variant : block-Jacobi form (block_L > 0): 0 = Alg. 3 as printed (left
+ *             preconditioning, rho = r^H p); 1 = textbook left PCG (rho =
+ *             r^H z); 2 = symmetric form (the system of Thm 4): A <- T A T^H,
+ *             b <- T b with T = blockdiag(C_i^{-1}), A_i = C_i C_i^H, the
+ *             Alg. 2 iteration on it, x = T^H x_bar.  All three give the
+ *             same iterates in exact arithmetic; 2 keeps the per-iteration
+ *             cost of plain CG.
  * Built combinations: gram_op == mv_op, and work = ip = (mv_op == F64 ? F64 : F32).
  */
 typedef struct {

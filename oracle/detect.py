@@ -76,7 +76,8 @@ class Schedule:
     work    : u_W, every other step (alpha, beta, x, r, p, z updates)
     refresh_every : FP64 residual replacement period (0 = off)
     refine_steps  : FP64 iterative-refinement steps through H (0 = off)
-    variant : 0 = Alg. 3 as printed (rho = r^H p); 1 = textbook PCG (rho = r^H z)
+    variant : 0 = Alg. 3 as printed (rho = r^H p); 1 = textbook PCG (rho = r^H z);
+              2 = symmetric (split) form: Alg. 2 on T A T^H, x = T^H x_bar
     fma     : u_W updates of the form a*b + c rounded once (True) or twice
     accum   : "exact": every matrix / inner product is summed exactly and rounded
               once (an idealised matrix core); "sequential": the same sums as a
@@ -446,6 +447,52 @@ def fp_cg(A, b, iters: int, sched: Schedule = FP64, mv=None, A_ref=None, trace=N
     return x, broken
 
 
+def bj_factor(A, L: int, work: str = "fp64"):
+    """T = blockdiag(C_1^{-1}, ..., C_d^{-1}) with A_i = C_i C_i^H (Cholesky), so
+    that M_d = T^H T (eq. pre_BJ).  Computed in FP64 and rounded to ``work``.
+    A block that is not numerically positive definite uses the inverse square
+    root of its diagonal (flagged).  Returns (T, not_pd)."""
+    Bn, K, _ = A.shape
+    if K % L:
+        raise ValueError("block size must divide K")
+    T = np.zeros_like(A, dtype=np.complex128)
+    not_pd = np.zeros(Bn, dtype=bool)
+    for j in range(K // L):
+        sl = slice(j * L, (j + 1) * L)
+        for c in range(Bn):
+            a = np.asarray(A[c, sl, sl], dtype=np.complex128)
+            try:
+                if not np.all(np.isfinite(a)):
+                    raise np.linalg.LinAlgError
+                import scipy.linalg as sla
+
+                # C^{-1} by forward substitution: exactly lower triangular
+                t = np.tril(sla.solve_triangular(np.linalg.cholesky(a), np.eye(L), lower=True))
+                if not np.all(np.isfinite(t)):
+                    raise np.linalg.LinAlgError
+            except np.linalg.LinAlgError:
+                not_pd[c] = True
+                dg = np.real(np.diag(a))
+                ok = np.isfinite(dg) & (dg > 0)
+                t = np.diag(np.where(ok, 1.0 / np.sqrt(np.where(ok, dg, 1.0)), 1.0)).astype(np.complex128)
+            T[c, sl, sl] = t
+    return fl(T, work), not_pd
+
+
+def split_system(A, T, work: str = "fp64"):
+    """A_bar = T A T^H (the symmetrically preconditioned Gram of Thm 4), formed
+    in FP64 from the u_W operands and rounded once to u_W; the upper triangle
+    is kept and mirrored so that A_bar is exactly Hermitian."""
+    Th = np.conj(np.swapaxes(T, -1, -2))
+    Ab = T @ A @ Th
+    K = A.shape[-1]
+    up = np.triu(np.ones((K, K), dtype=bool), 1)
+    Ab = np.where(up, Ab, np.conj(np.swapaxes(Ab, -1, -2)))
+    d = np.arange(K)
+    Ab[..., d, d] = np.real(Ab[..., d, d])
+    return fl(Ab, work)
+
+
 def bj_inverse(A, L: int, work: str = "fp64"):
     """eq. pre_BJ: M_d = blockdiag(A_1^{-1}, ..., A_d^{-1}) with L x L blocks.
 
@@ -486,8 +533,13 @@ def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, 
     """Alg. 3 (FP-BJ-CG), left-preconditioned.  Returns (x, broken).
 
     variant 0 follows the printed algorithm (rho_{i-1} = r^H p for alpha and for
-    beta's denominator); variant 1 is textbook PCG (rho = r^H z carried over).
+    beta's denominator); variant 1 is textbook PCG (rho = r^H z carried over);
+    variant 2 is the symmetric (split) form: Alg. 2 on A_bar = T A T^H with
+    b_bar = T b and x = T^H x_bar, T = blockdiag(C_i^{-1}) -- the system
+    Thm 4 analyses; in exact arithmetic all three give the same iterates.
     """
+    if sched.variant == 2:
+        return fp_bj_cg_split(A, b, iters, L, sched, A_ref=A_ref, trace=trace)[:2]
     P = _Prec(sched)
     mv = mv if mv is not None else MatVec(A, sched)
     if M is None:
@@ -524,6 +576,23 @@ def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, 
 # --------------------------------------------------------------------------
 # QAM slicer and bit errors
 # --------------------------------------------------------------------------
+def fp_bj_cg_split(A, b, iters: int, L: int, sched: Schedule = FP64, T=None, Abar=None, mv=None, A_ref=None,
+                   trace=None):
+    """Alg. 3 in its symmetric form: CG (Alg. 2 steps) on A_bar x_bar = b_bar,
+    then x = T^H x_bar.  Returns (x, broken, T, A_bar)."""
+    W = sched.work if not _is_exact(A) else "fp64"
+    if T is None:
+        T, _ = bj_factor(A, L, W)
+    if Abar is None:
+        Abar = split_system(A, T, W)
+    mv = mv if mv is not None else MatVec(Abar, sched)
+    bb = fl(T @ b, W) if not _is_exact(b) else T @ b
+    xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv, A_ref=Abar, trace=trace)
+    Th = np.conj(np.swapaxes(T, -1, -2))
+    x = fl(Th @ xb, W) if not _is_exact(xb) else Th @ xb
+    return x, broken, T, Abar
+
+
 def _gray(n):
     return n ^ (n >> 1)
 
@@ -585,13 +654,23 @@ def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64)
     A, b = gram(H, Y, sigma2, sched)
     nonfin = ~(np.all(np.isfinite(A), axis=(-2, -1)) & np.all(np.isfinite(b), axis=(-2, -1)))
     flags |= np.where(nonfin, FLAG_NONFINITE, 0).astype(np.uint32)
-    mv = MatVec(A, sched, flags)
-    M = None
+    M = T = Abar = None
+    split = bool(L) and sched.variant == 2
     if L:
-        M, not_pd = bj_inverse(A, L, sched.work)
+        if split:
+            T, not_pd = bj_factor(A, L, sched.work)
+            Abar = split_system(A, T, sched.work)
+        else:
+            M, not_pd = bj_inverse(A, L, sched.work)
         flags |= np.where(not_pd, FLAG_BLOCK_NOT_PD, 0).astype(np.uint32)
+    mv = MatVec(Abar if split else A, sched, flags)
 
-    def solve(rhs):
+    def solve(rhs, exact_back=False):
+        if split:
+            bb = fl(T @ rhs, sched.work)
+            xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv)
+            x = np.conj(np.swapaxes(T, -1, -2)) @ xb
+            return (x if exact_back else fl(x, sched.work)), broken
         if L:
             return fp_bj_cg(A, rhs, iters, L, sched, mv=mv, M=M)
         return fp_cg(A, rhs, iters, sched, mv=mv)
@@ -603,12 +682,20 @@ def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64)
         x = x.astype(np.complex128)
         s2 = np.asarray(sigma2, dtype=np.float64).reshape(-1, 1, 1)
         Hh = np.conj(np.swapaxes(H, -1, -2))
+        def solve_split_fp64(r):
+            bb = fl(T @ r, sched.work)
+            xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv)
+            return np.conj(np.swapaxes(T, -1, -2)) @ xb, broken    # x = T^H x_bar in FP64
+
         for _ in range(sched.refine_steps):
             res = Hh @ (Y - H @ x) - s2 * x                 # FP64, exact A
             amax = np.max(np.maximum(np.abs(res.real), np.abs(res.imag)), axis=-2, keepdims=True)
             sc = 1.0 / _pow2_floor(amax)
-            rhs = fl(res * sc, sched.work)
-            d, broken = solve(rhs)
+            if split:
+                # b_bar = T (r sc) formed in FP64 from the u_W factor and rounded once
+                d, broken = solve_split_fp64(res * sc)
+            else:
+                d, broken = solve(fl(res * sc, sched.work))
             flags |= np.where(broken, FLAG_BREAKDOWN, 0).astype(np.uint32)
             x = x + d.astype(np.complex128) / sc
         slice_prec = "fp64"

@@ -11,20 +11,28 @@
 //      Only the upper triangle of 16x16 complex tiles is formed; the lower
 //      one is its conjugate transpose.  A and B land in LDS in u_W.
 //   2. Block-Jacobi setup (eq. pre_BJ): every L x L diagonal block is
-//      Cholesky-factored and inverted explicitly, M_i = C^{-H} C^{-1}, one
-//      lane per block row.
-//   3. (P)CG (Alg. 2 / Alg. 3): the iterate vectors live in registers.  Lane
+//      Cholesky-factored, A_i = C_i C_i^H, and T_i = C_i^{-1} is formed by
+//      forward substitution, one lane per block row/column.  Alg. 3 as
+//      printed (left preconditioning) keeps M_i = T_i^H T_i and applies
+//      z = M_d r every iteration; its symmetric form (the system of Thm 4)
+//      instead rewrites A <- T A T^H and b <- T b once, runs the Alg. 2
+//      iteration on it and returns x = T^H x_bar.  On matrix cores the
+//      symmetric form keeps the per-iteration cost of plain CG: z = M_d r is
+//      fp32 vector work that costs more than the matrix-core product A p.
+//   3. (P)CG (Alg. 2 / Alg. 3): r and p live in registers, x in LDS.  Lane
 //      (g, n) of wave w owns column n and the SH complex entries
 //      (g*NW + w)*SH + e, e < SH, so Jacobi blocks (L | SH) are lane-local.
-//      A p runs on the matrix cores with the u_MV operands held in registers
-//      (contraction index packed in the lane's own slot order, so the output
-//      tile of one iteration is the input operand of the next without any
-//      data movement); inner products are lane-local FMA chains reduced over
-//      the four lane groups with cross-lane shuffles.
+//      A p runs on the matrix cores with the u_MV operands in registers or
+//      LDS (contraction index packed in the lane's own slot order, so the
+//      output tile of one iteration is the input operand of the next without
+//      any data movement); inner products are lane-local FMA chains reduced
+//      over the four lane groups with cross-lane shuffles.
 //   4. Optional FP64 residual refresh r = b - A x on the stored Gram, and FP64
 //      iterative refinement through H (r = H^H (y - H x) - sigma^2 x).
 //   5. QAM slicer epilogue and the x_hat / label stores.
 #pragma once
+
+#include <type_traits>
 
 #include "fpcg_device.hpp"
 
@@ -59,12 +67,17 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     using OG = Op<FMT, KPLG>;
     using Wt = typename O::work;
     static constexpr int NAV = NF * NW * NKB * 2;     // u_MV A-operand fragments per lane
-    static constexpr bool AREG = LOWP || (NAV * (int)sizeof(Wt) <= 256);
+    using frag = typename O::frag;
+    // A operand: registers when small, else fragment-ordered LDS copy (reduced
+    // precision) or read in place from the u_W Gram (fp32 / fp64)
+    static constexpr bool AREG = LOWP ? (NAV * (int)sizeof(frag) <= 128) : (NAV * (int)sizeof(Wt) <= 256);
+    static constexpr bool AFRAG_LDS = LOWP && !AREG;
     static constexpr int NPAIR = F * (F + 1) / 2;
     static constexpr int PPW = (NPAIR + NW - 1) / NW;
     static constexpr int MFPW = (F + NW - 1) / NW;
     static constexpr int LDA = KP + 1;
     static constexpr int RC = 16;                     // antennas per refinement chunk
+    static constexpr int NT = 64 * NW;
     // LDS layout in bytes
     static constexpr size_t W = sizeof(Wt);
     static constexpr size_t off_Ar = 0;
@@ -72,15 +85,22 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr size_t off_Br = off_Ai + W * KP * LDA;
     static constexpr size_t off_Bi = off_Br + W * KP * 16;
     static constexpr size_t off_M = off_Bi + W * KP * 16;
-    static constexpr size_t sz_M = LB ? 2 * W * KP * LB : 0;
-    static constexpr size_t off_S = off_M + sz_M;     // scratch region (BJ factors or exchange)
+    static constexpr size_t sz_M = LB ? 2 * W * KP * LB : 0;           // M_d or T blocks
+    static constexpr size_t off_X = off_M + sz_M;                       // x slots [2][SH][NT]
+    static constexpr size_t sz_X = 2 * W * SH * NT;
+    static constexpr size_t off_F = off_X + sz_X;                       // A operand fragments
+    static constexpr size_t sz_F = AFRAG_LDS ? (size_t)NAV * NT * sizeof(frag) : 0;
+    static constexpr size_t off_S = off_F + sz_F;                       // scratch: BJ factors or exchange
     static constexpr size_t sz_bj = LB ? 4 * W * KP * LB : 0;
-    static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * 8 : 0;    // P / x exchange (doubles)
+    static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * 8 : 0;    // p exchange (doubles)
     static constexpr size_t sz_red = (size_t)2 * NW * 16 * 4 * 8;                    // dot partials, 2 parities
     static constexpr size_t sz_ref = (NW > 1) ? (size_t)NW * RC * 16 * 2 * 8 : 0;   // refinement partials
     static constexpr size_t sz_ex = sz_xp + sz_red + sz_ref;
     static constexpr size_t sz_S = sz_bj > sz_ex ? sz_bj : sz_ex;
-    static constexpr size_t lds_bytes = off_S + sz_S;
+    static constexpr size_t lds_bytes = off_S + sz_S;                   // without refinement
+    static constexpr size_t off_X64 = lds_bytes;                        // FP64 iterate [2][SH][NT]
+    static constexpr size_t sz_X64 = 2 * 8 * (size_t)SH * NT;
+    static constexpr size_t lds_bytes_refine = off_X64 + sz_X64;
 };
 
 template <int KP, int NW, int FMT, int LB, typename IOT>
@@ -94,7 +114,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     using acc_t = typename O::acc;
     constexpr int SH = C::SH, NF = C::NF, NKB = C::NKB, F = C::F, KPL = C::KPL;
     constexpr int KPLG = C::KPLG, KBG = C::KBG, LDA = C::LDA, PPW = C::PPW, MFPW = C::MFPW;
-    constexpr int NT = 64 * NW;
+    constexpr int NT = C::NT;
 
     extern __shared__ __align__(16) unsigned char smem[];
     Wt* sAr = reinterpret_cast<Wt*>(smem + C::off_Ar);
@@ -103,6 +123,11 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     Wt* sBi = reinterpret_cast<Wt*>(smem + C::off_Bi);
     Wt* sMr = reinterpret_cast<Wt*>(smem + C::off_M);
     Wt* sMi = sMr + KP * (LB ? LB : 1);
+    Wt* sXr = reinterpret_cast<Wt*>(smem + C::off_X);                   // x, [SH][NT]
+    Wt* sXi = sXr + SH * NT;
+    frag* sF = reinterpret_cast<frag*>(smem + C::off_F);
+    double* sX64r = reinterpret_cast<double*>(smem + C::off_X64);      // refinement only
+    double* sX64i = sX64r + SH * NT;
     unsigned char* scr = smem + C::off_S;
     double* sXP = reinterpret_cast<double*>(scr);                       // [NW][64][2*SH]
     double* sRed = reinterpret_cast<double*>(scr + C::sz_xp);          // [2][NW][16][4]
@@ -281,18 +306,9 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     }
     __syncthreads();
 
-    // ------------------------------------------------------------ fp8 scale of A (u_MV operand)
-    int eA = 0;
-    if constexpr (FMT == F8) {
-        float ma = 0.f;
-        for (int i = tid; i < K * K; i += NT) {
-            const int r = i / K, c = i % K;
-            ma = fmaxf(ma, fmaxf(fabsf((float)sAr[r * LDA + c]), fabsf((float)sAi[r * LDA + c])));
-        }
-        ma = block_max(ma);
-        eA = fp8_scale_exp(ma);
-    }
-    const float sA = ldexpf(1.f, eA);
+
+    const bool split = (LB > 0) && (P.variant == 2);   // symmetric form of Alg. 3
+    const bool left = (LB > 0) && !split;             // Alg. 3 as printed / textbook PCG
 
     // ------------------------------------------------------------ 2. block-Jacobi setup (eq. pre_BJ)
     if constexpr (LB > 0) {
@@ -354,7 +370,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
         __syncthreads();
         const bool blk_bad = act && sBad[cb / LB] != 0u;
         __syncthreads();
-        // T = C^{-1}: this lane computes column i of T
+        // T = C^{-1}: this lane computes column i of T by forward substitution
         Wt tr[LB], ti[LB];
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
@@ -376,39 +392,121 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                 ti[r] = -si / crr;
             }
         }
+        if (blk_bad) {
+            // not positive definite: T = diag(a_ii)^{-1/2}, so M_d = diag(a_ii)^{-1}
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                tr[r] = 0; ti[r] = 0;
+                if (r == i) tr[r] = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / sqrt(diag) : (Wt)1;
+            }
+        }
+        Wt* dTr = split ? sMr : sTr;                  // the symmetric form keeps T itself
+        Wt* dTi = split ? sMi : sTi;
         if (act) {
 #pragma unroll
             for (int r = 0; r < LB; ++r) {
-                sTr[(cb + r) * LB + i] = tr[r];
-                sTi[(cb + r) * LB + i] = ti[r];
-            }
-        }
-        __syncthreads();
-        // M = T^H T: row i
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < LB; ++j) {
-                Wt mr = 0, mi = 0;
-#pragma unroll
-                for (int m = 0; m < LB; ++m) {
-                    if (m >= i && m >= j) {
-                        const Wt ar_ = sTr[(cb + m) * LB + i], ai_ = sTi[(cb + m) * LB + i];   // T[m][i]
-                        const Wt br_ = sTr[(cb + m) * LB + j], bi_ = sTi[(cb + m) * LB + j];   // T[m][j]
-                        mr = mr + (ar_ * br_ + ai_ * bi_);
-                        mi = mi + (ar_ * bi_ - ai_ * br_);
-                    }
-                }
-                if (blk_bad) {
-                    mr = 0; mi = 0;
-                    if (j == i) mr = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / diag : (Wt)1;
-                }
-                sMr[(cb + i) * LB + j] = mr;
-                sMi[(cb + i) * LB + j] = mi;
+                dTr[(cb + r) * LB + i] = tr[r];
+                dTi[(cb + r) * LB + i] = ti[r];
             }
             if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
         }
         __syncthreads();
+        if (!split) {
+            // M = T^H T: row i
+            if (act) {
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    Wt mr = 0, mi = 0;
+#pragma unroll
+                    for (int m = 0; m < LB; ++m) {
+                        if (m >= i && m >= j) {
+                            const Wt ar_ = sTr[(cb + m) * LB + i], ai_ = sTi[(cb + m) * LB + i];   // T[m][i]
+                            const Wt br_ = sTr[(cb + m) * LB + j], bi_ = sTi[(cb + m) * LB + j];   // T[m][j]
+                            mr = mr + (ar_ * br_ + ai_ * bi_);
+                            mi = mi + (ar_ * bi_ - ai_ * br_);
+                        }
+                    }
+                    sMr[(cb + i) * LB + j] = mr;
+                    sMi[(cb + i) * LB + j] = mi;
+                }
+            }
+            __syncthreads();
+        } else {
+            // A <- T A T^H in place: W = A T^H row by row (thread = row), then
+            // T W column by column (thread = column); T is block lower triangular
+            if (act) {
+                const int m = tid;
+#pragma unroll 1
+                for (int c0 = 0; c0 < KP; c0 += LB) {
+                    Wt a_r[LB], a_i[LB];
+#pragma unroll
+                    for (int j = 0; j < LB; ++j) { a_r[j] = sAr[m * LDA + c0 + j]; a_i[j] = sAi[m * LDA + c0 + j]; }
+#pragma unroll
+                    for (int c = 0; c < LB; ++c) {
+                        Wt wr = 0, wi = 0;
+#pragma unroll
+                        for (int j = 0; j <= c; ++j) {          // w += a_j conj(T[c][j])
+                            const Wt t_r = sMr[(c0 + c) * LB + j], t_i = sMi[(c0 + c) * LB + j];
+                            wr = fma(a_r[j], t_r, wr);
+                            wr = fma(a_i[j], t_i, wr);
+                            wi = fma(a_i[j], t_r, wi);
+                            wi = fma(-a_r[j], t_i, wi);
+                        }
+                        sAr[m * LDA + c0 + c] = wr;
+                        sAi[m * LDA + c0 + c] = wi;
+                    }
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const int c = tid;
+#pragma unroll 1
+                for (int r0 = 0; r0 < KP; r0 += LB) {
+                    Wt w_r[LB], w_i[LB];
+#pragma unroll
+                    for (int j = 0; j < LB; ++j) { w_r[j] = sAr[(r0 + j) * LDA + c]; w_i[j] = sAi[(r0 + j) * LDA + c]; }
+#pragma unroll
+                    for (int r = 0; r < LB; ++r) {
+                        Wt vr = 0, vi = 0;
+#pragma unroll
+                        for (int j = 0; j <= r; ++j) {          // v += T[r][j] w_j
+                            const Wt t_r = sMr[(r0 + r) * LB + j], t_i = sMi[(r0 + r) * LB + j];
+                            vr = fma(t_r, w_r[j], vr);
+                            vr = fma(-t_i, w_i[j], vr);
+                            vi = fma(t_r, w_i[j], vi);
+                            vi = fma(t_i, w_r[j], vi);
+                        }
+                        sAr[(r0 + r) * LDA + c] = vr;
+                        sAi[(r0 + r) * LDA + c] = vi;
+                    }
+                }
+            }
+            __syncthreads();
+            // exactly Hermitian: lower triangle = conjugate of the upper one, real diagonal
+            if (act) {
+                const int r = tid;
+                for (int c = 0; c < r; ++c) {
+                    sAr[r * LDA + c] = sAr[c * LDA + r];
+                    sAi[r * LDA + c] = -sAi[c * LDA + r];
+                }
+                sAi[r * LDA + r] = 0;
+            }
+            __syncthreads();
+        }
     }
+
+    // ------------------------------------------------------------ fp8 scale of the u_MV matrix
+    int eA = 0;
+    if constexpr (FMT == F8) {
+        float ma = 0.f;
+        for (int i = tid; i < K * K; i += NT) {
+            const int r = i / K, c = i % K;
+            ma = fmaxf(ma, fmaxf(fabsf((float)sAr[r * LDA + c]), fabsf((float)sAi[r * LDA + c])));
+        }
+        ma = block_max(ma);
+        eA = fp8_scale_exp(ma);
+    }
+    const float sA = ldexpf(1.f, eA);
 
     // ------------------------------------------------------------ u_MV operand of A
     // A-operand lane (g, n) of output tile phi holds row rowc(phi) (fixed per lane)
@@ -425,8 +523,9 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
         return (gm * NW + wave) * SH + 4 * phi + im;
     };
     auto colc = [&](int ws, int kb, int j) -> int { return (g * NW + ws) * SH + kb * KPL + j; };
-    frag afr[C::AREG ? NF : 1][C::AREG ? NW : 1][C::AREG ? NKB : 1][2];
-    if constexpr (C::AREG) {
+    auto fidx = [&](int phi, int ws, int kb, int ri) -> int { return ((phi * NW + ws) * NKB + kb) * 2 + ri; };
+    frag afr[C::AREG ? C::NAV : 1];
+    if constexpr (C::AREG || C::AFRAG_LDS) {
 #pragma unroll
         for (int phi = 0; phi < NF; ++phi)
 #pragma unroll
@@ -440,13 +539,21 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                         vr[j] = sAr[rr_ * LDA + colc(ws, kb, j)];
                         vi[j] = sAi[rr_ * LDA + colc(ws, kb, j)];
                     }
-                    afr[phi][ws][kb][0] = O::pack(vr, sA);
-                    afr[phi][ws][kb][1] = O::pack(vi, sA);
+                    const frag fr = O::pack(vr, sA), fi = O::pack(vi, sA);
+                    if constexpr (C::AREG) {
+                        afr[fidx(phi, ws, kb, 0)] = fr;
+                        afr[fidx(phi, ws, kb, 1)] = fi;
+                    } else {
+                        sF[fidx(phi, ws, kb, 0) * NT + tid] = fr;
+                        sF[fidx(phi, ws, kb, 1) * NT + tid] = fi;
+                    }
                 }
     }
     auto A_op = [&](int phi, int ws, int kb, int ri) -> frag {
         if constexpr (C::AREG) {
-            return afr[phi][ws][kb][ri];
+            return afr[fidx(phi, ws, kb, ri)];
+        } else if constexpr (C::AFRAG_LDS) {
+            return sF[fidx(phi, ws, kb, ri) * NT + tid];
         } else {
             const Wt* src = ri ? sAi : sAr;
             Wt v = src[rowc(phi) * LDA + colc(ws, kb, 0)];
@@ -482,7 +589,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             parity ^= 1;
         }
     };
-    // publish this wave's slots of two vectors (NW > 1) so that other waves can read them
+    // publish this wave's slots of p (NW > 1) so that other waves can read them
     auto publish = [&](const Wt* vr, const Wt* vi) {
         if constexpr (NW > 1) {
             double* dst = sXP + ((size_t)wave * 64 + lane) * 2 * SH;
@@ -494,14 +601,14 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
         return (Wt)sXP[((size_t)ws * 64 + lane) * 2 * SH + part * SH + e];
     };
 
+    const int base_c = (g * NW + wave) * SH;
     // z = M r (block-diagonal, lane-local, u_W)
     auto apply_M = [&](const Wt* rr, const Wt* ri, Wt* zr, Wt* zi) {
         if constexpr (LB > 0) {
-            const int base = (g * NW + wave) * SH;
 #pragma unroll
             for (int e = 0; e < SH; ++e) {
                 const int j0 = (e / LB) * LB;
-                const int c = base + e;
+                const int c = base_c + e;
                 Wt ar = 0, ai = 0;
 #pragma unroll
                 for (int j = 0; j < LB; ++j) {
@@ -519,21 +626,72 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             for (int e = 0; e < SH; ++e) { zr[e] = rr[e]; zi[e] = ri[e]; }
         }
     };
-
-    const int base_c = (g * NW + wave) * SH;
-    double x64r[SH], x64i[SH];
-    Wt xr[SH], xi[SH];
+    // v <- T v (b_bar = T b) and v <- T^H v (x = T^H x_bar), lane-local, in arithmetic type Ta
+    auto apply_T = [&](auto* vr, auto* vi) {
+        using Ta = typename std::remove_reference<decltype(vr[0])>::type;
+        if constexpr (LB > 0) {
 #pragma unroll
-    for (int e = 0; e < SH; ++e) { x64r[e] = 0; x64i[e] = 0; }
+            for (int b0 = 0; b0 < SH; b0 += LB) {
+                Ta ur[LB], ui[LB];
+#pragma unroll
+                for (int r = 0; r < LB; ++r) {
+                    const int c = base_c + b0 + r;
+                    Ta sr = 0, si = 0;
+#pragma unroll
+                    for (int j = 0; j <= r; ++j) {
+                        const Ta t_r = (Ta)sMr[c * LB + j], t_i = (Ta)sMi[c * LB + j];
+                        sr = fma(t_r, vr[b0 + j], sr);
+                        sr = fma(-t_i, vi[b0 + j], sr);
+                        si = fma(t_r, vi[b0 + j], si);
+                        si = fma(t_i, vr[b0 + j], si);
+                    }
+                    ur[r] = sr;
+                    ui[r] = si;
+                }
+#pragma unroll
+                for (int r = 0; r < LB; ++r) { vr[b0 + r] = ur[r]; vi[b0 + r] = ui[r]; }
+            }
+        }
+    };
+    auto apply_TH = [&](auto* vr, auto* vi) {
+        using Ta = typename std::remove_reference<decltype(vr[0])>::type;
+        if constexpr (LB > 0) {
+#pragma unroll
+            for (int b0 = 0; b0 < SH; b0 += LB) {
+                Ta ur[LB], ui[LB];
+                const int cb0 = base_c + b0;
+#pragma unroll
+                for (int r = 0; r < LB; ++r) {
+                    Ta sr = 0, si = 0;
+#pragma unroll
+                    for (int j = r; j < LB; ++j) {          // += conj(T[j][r]) v_j
+                        const Ta t_r = (Ta)sMr[(cb0 + j) * LB + r], t_i = (Ta)sMi[(cb0 + j) * LB + r];
+                        sr = fma(t_r, vr[b0 + j], sr);
+                        sr = fma(t_i, vi[b0 + j], sr);
+                        si = fma(t_r, vi[b0 + j], si);
+                        si = fma(-t_i, vr[b0 + j], si);
+                    }
+                    ur[r] = sr;
+                    ui[r] = si;
+                }
+#pragma unroll
+                for (int r = 0; r < LB; ++r) { vr[b0 + r] = ur[r]; vi[b0 + r] = ui[r]; }
+            }
+        }
+    };
 
     const int passes = 1 + P.refine_steps;
     int es = 0;                                       // exponent of the current pass's residual scale
     for (int pass = 0; pass < passes; ++pass) {
         if (pass > 0) {
             // -------------------------------------------- FP64 residual through H
-            double resr[SH], resi[SH];
+            double resr[SH], resi[SH], x64r[SH], x64i[SH];
 #pragma unroll
-            for (int e = 0; e < SH; ++e) { resr[e] = 0; resi[e] = 0; }
+            for (int e = 0; e < SH; ++e) {
+                resr[e] = 0; resi[e] = 0;
+                x64r[e] = sX64r[e * NT + tid];
+                x64i[e] = sX64i[e * NT + tid];
+            }
             if constexpr (NW == 1) {
                 // one antenna at a time: e_a = y_a - h_a x (column sums), res += conj(h_a) e_a
 #pragma unroll 1
@@ -570,17 +728,15 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                     for (int u = 0; u < C::RC; ++u) {
                         const int a = a0 + u;
                         double sr = 0, si = 0;
-                        if (a < Nbs) {
 #pragma unroll
-                            for (int e = 0; e < SH; ++e) {
-                                const int c = base_c + e;
-                                double hr, hi;
-                                CxB<IOT>::load(bH, hofs(a, c), hr, hi);
-                                sr = fma(hr, x64r[e], sr);
-                                sr = fma(-hi, x64i[e], sr);
-                                si = fma(hr, x64i[e], si);
-                                si = fma(hi, x64r[e], si);
-                            }
+                        for (int e = 0; e < SH; ++e) {
+                            const int c = base_c + e;
+                            double hr, hi;
+                            CxB<IOT>::load(bH, hofs(a, c), hr, hi);
+                            sr = fma(hr, x64r[e], sr);
+                            sr = fma(-hi, x64i[e], sr);
+                            si = fma(hr, x64i[e], si);
+                            si = fma(hi, x64r[e], si);
                         }
                         sr = col_sum(sr);
                         si = col_sum(si);
@@ -647,23 +803,42 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             }
             const double sc = ldexp(1.0, -es);
 #pragma unroll
+            for (int e = 0; e < SH; ++e) { resr[e] *= sc; resi[e] *= sc; }
+            if (split) apply_T(resr, resi);             // b_bar = T (r sc), FP64 arithmetic
+#pragma unroll
             for (int e = 0; e < SH; ++e) {
                 const int c = base_c + e;
-                sBr[c * 16 + n] = (Wt)(resr[e] * sc);
-                sBi[c * 16 + n] = (Wt)(resi[e] * sc);
+                sBr[c * 16 + n] = (Wt)resr[e];
+                sBi[c * 16 + n] = (Wt)resi[e];
             }
             __syncthreads();
         }
 
         // ------------------------------------------------ 3. (P)CG
-        Wt rr[SH], ri[SH], pr[SH], pi[SH], wr[SH], wi[SH], zr[SH], zi[SH];
+        Wt rr[SH], ri[SH], pr[SH], pi[SH];
+        {
+            Wt wr[SH], wi[SH];
 #pragma unroll
-        for (int e = 0; e < SH; ++e) {
-            xr[e] = 0; xi[e] = 0;
-            rr[e] = sBr[(base_c + e) * 16 + n];
-            ri[e] = sBi[(base_c + e) * 16 + n];
+            for (int e = 0; e < SH; ++e) {
+                sXr[e * NT + tid] = 0;
+                sXi[e * NT + tid] = 0;
+                rr[e] = sBr[(base_c + e) * 16 + n];
+                ri[e] = sBi[(base_c + e) * 16 + n];
+            }
+            if (split && pass == 0) apply_T(rr, ri);     // b_bar = T b
+            if (split && pass == 0) {
+                // keep b_bar for the FP64 refresh
+#pragma unroll
+                for (int e = 0; e < SH; ++e) { sBr[(base_c + e) * 16 + n] = rr[e]; sBi[(base_c + e) * 16 + n] = ri[e]; }
+            }
+            if (left) apply_M(rr, ri, wr, wi);         // p0 = M r0 (Alg. 3) or r0
+            else {
+#pragma unroll
+                for (int e = 0; e < SH; ++e) { wr[e] = rr[e]; wi[e] = ri[e]; }
+            }
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { pr[e] = wr[e]; pi[e] = wi[e]; }
         }
-        apply_M(rr, ri, pr, pi);                       // p0 = M r0 (Alg. 3) or r0 (Alg. 2)
         Wt rho_cur;
         {
             Wt v[4];
@@ -714,6 +889,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                     }
                 }
             }
+            Wt wr[SH], wi[SH];
             const Wt inv_s = (Wt)(ldexpf(1.f, -eA)), inv_p = (Wt)(ldexpf(1.f, -eP));
 #pragma unroll
             for (int phi = 0; phi < NF; ++phi)
@@ -734,7 +910,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                 v[1] = fma(rr[e], pr[e], v[1]);
                 v[1] = fma(ri[e], pi[e], v[1]);
             }
-            const bool need_rp = (LB > 0) && (P.variant == 0);
+            const bool need_rp = left && (P.variant == 0);
             col_reduce(v, need_rp ? 2 : 1);
             const Wt ph = v[0];
             const Wt rho_prev = need_rp ? v[1] : rho_cur;
@@ -746,19 +922,15 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                 const Wt alpha = rho_prev / ph;
 #pragma unroll
                 for (int e = 0; e < SH; ++e) {
-                    xr[e] = fma(alpha, pr[e], xr[e]);
-                    xi[e] = fma(alpha, pi[e], xi[e]);
+                    sXr[e * NT + tid] = fma(alpha, pr[e], sXr[e * NT + tid]);
+                    sXi[e * NT + tid] = fma(alpha, pi[e], sXi[e * NT + tid]);
                     rr[e] = fma(-alpha, wr[e], rr[e]);
                     ri[e] = fma(-alpha, wi[e], ri[e]);
                 }
             }
-            // ---- FP64 residual refresh on the stored Gram
+            // ---- FP64 residual refresh on the stored Gram (A, or T A T^H)
             if (P.refresh_every > 0 && it % P.refresh_every == 0 && it < P.iters) {
-                if constexpr (NW > 1) {
-                    __syncthreads();
-                    publish(xr, xi);
-                    __syncthreads();
-                }
+                if constexpr (NW > 1) __syncthreads();   // x of every wave visible
                 f64x4 Rr[NF], Ri[NF];
 #pragma unroll
                 for (int phi = 0; phi < NF; ++phi) { Rr[phi] = f64x4{0, 0, 0, 0}; Ri[phi] = f64x4{0, 0, 0, 0}; }
@@ -766,9 +938,8 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                 for (int ws = 0; ws < NW; ++ws) {
 #pragma unroll
                     for (int kb = 0; kb < SH; ++kb) {
-                        double bx, by;
-                        if (NW == 1 || ws == wave) { bx = (double)xr[kb]; by = (double)xi[kb]; }
-                        else { bx = (double)fetch(ws, kb, 0); by = (double)fetch(ws, kb, 1); }
+                        const double bx = (double)sXr[kb * NT + ws * 64 + lane];
+                        const double by = (double)sXi[kb * NT + ws * 64 + lane];
                         const int cc = (g * NW + ws) * SH + kb;
 #pragma unroll
                         for (int phi = 0; phi < NF; ++phi) {
@@ -793,9 +964,15 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                             ri[e] = (Wt)(b_i - Ri[phi][jj]);
                         }
                 }
+                if constexpr (NW > 1) __syncthreads();   // before x changes again
             }
-            // ---- z = M r, rho_i, beta, p
-            apply_M(rr, ri, zr, zi);
+            // ---- z = M r (left form) or r, rho_i, beta, p
+            Wt zr[SH], zi[SH];
+            if (left) apply_M(rr, ri, zr, zi);
+            else {
+#pragma unroll
+                for (int e = 0; e < SH; ++e) { zr[e] = rr[e]; zi[e] = ri[e]; }
+            }
             v[0] = 0;
 #pragma unroll
             for (int e = 0; e < SH; ++e) { v[0] = fma(rr[e], zr[e], v[0]); v[0] = fma(ri[e], zi[e], v[0]); }
@@ -812,42 +989,54 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             rho_cur = rho_new;
         }
         if (broken) myflag |= FLAG_BREAKDOWN;
+        // ------------------------------------------------ back-transform and refinement bookkeeping
         if (pass == 0) {
+            Wt xo_r[SH], xo_i[SH];
 #pragma unroll
-            for (int e = 0; e < SH; ++e) { x64r[e] = (double)xr[e]; x64i[e] = (double)xi[e]; }
+            for (int e = 0; e < SH; ++e) { xo_r[e] = sXr[e * NT + tid]; xo_i[e] = sXi[e * NT + tid]; }
+            if (split) apply_TH(xo_r, xo_i);           // x = T^H x_bar  (u_W)
+            if (P.refine_steps > 0) {
+#pragma unroll
+                for (int e = 0; e < SH; ++e) { sX64r[e * NT + tid] = (double)xo_r[e]; sX64i[e * NT + tid] = (double)xo_i[e]; }
+            } else if (colv) {
+                // ---- 5. slicer + stores (no refinement)
+                const Wt nu = (Wt)P.nu, mm = (Wt)P.m;
+#pragma unroll
+                for (int e = 0; e < SH; ++e) {
+                    const int c = base_c + e;
+                    if (c < K) {
+                        const int64_t o = (ch * K + c) * (int64_t)R + col;
+                        Cx<IOT>::store(P.xhat, o, xo_r[e], xo_i[e]);
+                        P.labels[o] = slice_label<Wt>(xo_r[e], xo_i[e], nu, mm, P.m, P.bits);
+                    }
+                }
+            }
         } else {
+            double dr[SH], di[SH];
+#pragma unroll
+            for (int e = 0; e < SH; ++e) { dr[e] = (double)sXr[e * NT + tid]; di[e] = (double)sXi[e * NT + tid]; }
+            if (split) apply_TH(dr, di);               // d = T^H d_bar  (FP64 arithmetic)
             const double us = ldexp(1.0, es);          // x += d / sc, exact scaling
 #pragma unroll
             for (int e = 0; e < SH; ++e) {
-                x64r[e] = x64r[e] + (double)xr[e] * us;
-                x64i[e] = x64i[e] + (double)xi[e] * us;
+                sX64r[e * NT + tid] = sX64r[e * NT + tid] + dr[e] * us;
+                sX64i[e * NT + tid] = sX64i[e * NT + tid] + di[e] * us;
             }
         }
+        if constexpr (NW > 1) __syncthreads();
     }
 
-    // ------------------------------------------------------------ 5. slicer + stores
-    if (colv) {
-        if (P.refine_steps > 0) {
-            const double nu = P.nu, mm = (double)P.m;
+    // ------------------------------------------------------------ 5. slicer + stores (refined, FP64)
+    if (colv && P.refine_steps > 0) {
+        const double nu = P.nu, mm = (double)P.m;
 #pragma unroll
-            for (int e = 0; e < SH; ++e) {
-                const int c = base_c + e;
-                if (c < K) {
-                    const int64_t o = (ch * K + c) * (int64_t)R + col;
-                    Cx<IOT>::store(P.xhat, o, x64r[e], x64i[e]);
-                    P.labels[o] = slice_label<double>(x64r[e], x64i[e], nu, mm, P.m, P.bits);
-                }
-            }
-        } else {
-            const Wt nu = (Wt)P.nu, mm = (Wt)P.m;
-#pragma unroll
-            for (int e = 0; e < SH; ++e) {
-                const int c = base_c + e;
-                if (c < K) {
-                    const int64_t o = (ch * K + c) * (int64_t)R + col;
-                    Cx<IOT>::store(P.xhat, o, xr[e], xi[e]);
-                    P.labels[o] = slice_label<Wt>(xr[e], xi[e], nu, mm, P.m, P.bits);
-                }
+        for (int e = 0; e < SH; ++e) {
+            const int c = base_c + e;
+            if (c < K) {
+                const int64_t o = (ch * K + c) * (int64_t)R + col;
+                const double xr = sX64r[e * NT + tid], xi = sX64i[e * NT + tid];
+                Cx<IOT>::store(P.xhat, o, xr, xi);
+                P.labels[o] = slice_label<double>(xr, xi, nu, mm, P.m, P.bits);
             }
         }
     }

@@ -58,7 +58,7 @@ static int pick_kp(int K, int FMT, int L) {
     static const int kps[] = {16, 32, 64};
     for (int kp : kps) {
         if (kp < K) continue;
-        const int sh = kp / (4 * waves_for(kp));
+        const int sh = kp / (4 * waves_for(kp, FMT));
         if (L > sh) continue;
         if (FMT == F8 && kp < 32) continue;
         if (!find_entry(kp, FMT, L, 1)) continue;
@@ -87,7 +87,7 @@ fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
     if (s->refresh_every < 0) return fail(FPCG_E_INVAL, "refresh_every=%d must be >= 0", s->refresh_every);
     if (s->refine_steps < 0 || s->refine_steps > 16)
         return fail(FPCG_E_INVAL, "refine_steps=%d must be in [0, 16]", s->refine_steps);
-    if (s->variant != 0 && s->variant != 1) return fail(FPCG_E_INVAL, "variant=%d must be 0 or 1", s->variant);
+    if (s->variant < 0 || s->variant > 2) return fail(FPCG_E_INVAL, "variant=%d must be 0, 1 or 2", s->variant);
     if (s->gram_op != s->mv_op)
         return fail(FPCG_E_UNSUPPORTED, "gram_op (%d) must equal mv_op (%d)", s->gram_op, s->mv_op);
     const int want_work = s->mv_op == FPCG_F64 ? FPCG_F64 : FPCG_F32;
@@ -140,7 +140,8 @@ fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int6
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         for (const auto& t : table())
-            if (t.lds > 65536) (void)hipFuncSetAttribute(t.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.lds);
+            if (t.lds_refine > 65536)
+                (void)hipFuncSetAttribute(t.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.lds_refine);
     });
     (void)device;
     if (flags && R > 16) {   // several workgroups per channel OR their flags together
@@ -157,7 +158,7 @@ fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int6
     while ((1 << p.bits) < p.m) ++p.bits;
     p.nu = std::sqrt(2.0 * (qam - 1) / 3.0);
     dim3 grid((unsigned)B, (unsigned)((R + 15) / 16));
-    e->launch(p, grid, stream);
+    e->launch(p, grid, plan.sched.refine_steps > 0 ? e->lds_refine : e->lds, stream);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(FPCG_E_DEVICE, "fused kernel launch: %s", hipGetErrorString(err));
     return FPCG_OK;

@@ -77,7 +77,8 @@ def test_check_rejects_bad_schedules(fp):
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(9, 9, 1, 1, 0, 0, 0)) == -1
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, -1, 0, 0)) == -1
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, 0, 99, 0)) == -1
-    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, 0, 0, 2)) == -1
+    assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 1, 1, 1, 0, 0, 3)) == -1
+    assert fp.check(4, 64, 8, 1, 16, 8, 4, S(1, 1, 1, 1, 0, 0, 2)) == 0
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(1, 2, 1, 1, 0, 0, 0)) == -4   # gram_op != mv_op
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(2, 2, 0, 0, 0, 0, 0)) == -4   # FP64 work with bf16 operands
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(0, 0, 1, 1, 0, 0, 0)) == -4   # FP32 work with FP64 operands

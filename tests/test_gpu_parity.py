@@ -57,23 +57,24 @@ def test_fp64_c1_matches_oracle_to_1e12():
     assert not fl.any()
 
 
-@pytest.mark.parametrize("K,L,Nbs", [(32, 0, 128), (32, 8, 128), (64, 0, 256), (64, 8, 256), (20, 4, 50)])
-def test_fp64_converged_matches_oracle_to_1e12(K, L, Nbs):
+@pytest.mark.parametrize("K,L,Nbs,variant", [(32, 0, 128, 0), (32, 8, 128, 0), (64, 0, 256, 0), (64, 8, 256, 0),
+                                             (20, 4, 50, 0), (32, 8, 128, 2), (64, 8, 256, 2), (20, 4, 50, 2)])
+def test_fp64_converged_matches_oracle_to_1e12(K, L, Nbs, variant):
     wl = _wl(6, Nbs, K, 14, 64, 20.0, 0.5, 2)
     iters = 3 * K
-    _say(f"case fp64 converged K={K} L={L} I={iters}")
-    x, lab, fl = gpu_detect(wl, 64, iters, L, "fp64")
-    ref = oracle_detect(wl, 64, iters, L, "fp64")
+    _say(f"case fp64 converged K={K} L={L} variant={variant} I={iters}")
+    x, lab, fl = gpu_detect(wl, 64, iters, L, "fp64", variant=variant)
+    ref = oracle_detect(wl, 64, iters, L, "fp64", variant=variant)
     assert np.max(col_rel(x, ref.xhat)) < 1e-12
     ok, n, bad = labels_consistent(lab, ref.labels, x, ref.xhat, 64)
     assert ok, (n, bad)
 
 
-@pytest.mark.parametrize("L", [0, 4, 8])
-def test_fp32_converged_within_1e5_of_lmmse(L):
+@pytest.mark.parametrize("L,variant", [(0, 0), (4, 0), (8, 0), (8, 2)])
+def test_fp32_converged_within_1e5_of_lmmse(L, variant):
     wl = _wl(8, 128, 32, 14, 64, 20.0, 0.5, 3)
-    _say(f"case fp32 converged L={L}")
-    x, lab, fl = gpu_detect(wl, 64, 64, L, "fp32", np.complex64)
+    _say(f"case fp32 converged L={L} variant={variant}")
+    x, lab, fl = gpu_detect(wl, 64, 64, L, "fp32", np.complex64, variant=variant)
     A, b = D.gram(wl.H.astype(np.complex64).astype(np.complex128), wl.Y.astype(np.complex64).astype(np.complex128),
                   wl.sigma2)
     xs = D.lmmse(A, b)
@@ -106,15 +107,15 @@ SHORT_MAX = {"fp64": 1e-13, "fp32": 1e-5, "bf16": 1e-3, "fp16": 1e-3, "fp8": 1e-
 
 
 @pytest.mark.parametrize("sched", ["fp64", "fp32", "bf16", "fp16", "fp8"])
-@pytest.mark.parametrize("L", [0, 8])
-def test_short_horizon_parity(sched, L):
+@pytest.mark.parametrize("L,variant", [(0, 0), (8, 0), (8, 2)])
+def test_short_horizon_parity(sched, L, variant):
     io = np.complex128 if sched == "fp64" else np.complex64
     wl = _wl(10, 128, 32, 14, 64, 20.0, 0.5, 5)
     for it in (1, 2):
-        x, lab, fl = gpu_detect(wl, 64, it, L, sched, io)
-        ref = oracle_detect(wl, 64, it, L, sched, io)
+        x, lab, fl = gpu_detect(wl, 64, it, L, sched, io, variant=variant)
+        ref = oracle_detect(wl, 64, it, L, sched, io, variant=variant)
         e = col_rel(x, ref.xhat)
-        _say(f"case short {sched} L={L} I={it}: median {np.median(e):.2e} max {e.max():.2e}")
+        _say(f"case short {sched} L={L} v{variant} I={it}: median {np.median(e):.2e} max {e.max():.2e}")
         assert np.median(e) <= SHORT_MED[sched] * it and e.max() <= SHORT_MAX[sched] * it
 
 
@@ -137,6 +138,14 @@ CASES = [
     ("ragged-K20-N50-R17-bf16-L4", 5, 50, 20, 17, 16, 15.0, 0.3, 12, 4, "bf16", np.complex64, 0, 0),
     ("ragged-K12-N40-R3-fp16-refresh3", 5, 40, 12, 3, 256, 25.0, 0.2, 10, 4, "fp16", np.complex64, 3, 0),
     ("K16-fp16-L4", 5, 64, 16, 5, 16, 15.0, 0.5, 12, 4, "fp16", np.complex64, 0, 0),
+    # symmetric (split) form of the block-Jacobi preconditioner
+    ("c2-bf16-L8-split", 8, 128, 32, 14, 64, 20.0, 0.5, 12, 8, "bf16", np.complex64, 0, 2),
+    ("c2-fp8-L8-split", 8, 128, 32, 14, 64, 20.0, 0.5, 12, 8, "fp8", np.complex64, 0, 2),
+    ("c3-fp64-L8-split", 5, 256, 64, 14, 64, 15.0, 0.7, 24, 8, "fp64", np.complex128, 0, 2),
+    ("c3-fp16-L8-split-refresh4", 5, 256, 64, 14, 64, 15.0, 0.7, 16, 8, "fp16", np.complex64, 4, 2),
+    ("c3-fp8-L8-split", 5, 256, 64, 14, 64, 15.0, 0.7, 16, 8, "fp8", np.complex64, 0, 2),
+    ("ragged-K20-N50-R17-fp32-L4-split", 5, 50, 20, 17, 16, 15.0, 0.3, 12, 4, "fp32", np.complex128, 0, 2),
+    ("ragged-K12-N40-R3-bf16-L4-split-refresh3", 5, 40, 12, 3, 256, 25.0, 0.2, 10, 4, "bf16", np.complex64, 3, 2),
 ]
 
 
@@ -154,12 +163,13 @@ def test_fixed_iteration_parity(case):
 
 
 # --------------------------------------------------------------- refinement
-@pytest.mark.parametrize("sched,steps", [("fp16", 1), ("fp8", 1), ("fp8", 2), ("bf16", 2), ("fp32", 1)])
-def test_refinement_reaches_oracle_accuracy(sched, steps):
-    _say(f"case refine {sched} x{steps}")
+@pytest.mark.parametrize("sched,steps,variant", [("fp16", 1, 0), ("fp8", 1, 0), ("fp8", 2, 0), ("bf16", 2, 0),
+                                                 ("fp32", 1, 0), ("fp16", 1, 2), ("fp8", 2, 2)])
+def test_refinement_reaches_oracle_accuracy(sched, steps, variant):
+    _say(f"case refine {sched} x{steps} variant={variant}")
     wl = _wl(8, 128, 32, 14, 64, 25.0, 0.5, 21)
-    x, lab, fl = gpu_detect(wl, 64, 16, 8, sched, np.complex64, refine=steps)
-    ref = oracle_detect(wl, 64, 16, 8, sched, np.complex64, refine=steps)
+    x, lab, fl = gpu_detect(wl, 64, 16, 8, sched, np.complex64, refine=steps, variant=variant)
+    ref = oracle_detect(wl, 64, 16, 8, sched, np.complex64, refine=steps, variant=variant)
     A, b = D.gram(wl.H.astype(np.complex64).astype(np.complex128), wl.Y.astype(np.complex64).astype(np.complex128),
                   wl.sigma2)
     xs = D.lmmse(A, b)
@@ -277,11 +287,11 @@ def test_operand_rounding_bitwise(fmt):
 
 
 # --------------------------------------------------------------- full-size sampled parity
-@pytest.mark.parametrize("cfg,sched,L,iters,refresh", [
-    ("c2", "bf16", 0, 16, 0), ("c2", "fp32", 0, 16, 0), ("c2", "fp64", 0, 16, 0),
-    ("c3", "fp16", 8, 16, 4), ("c3", "fp64", 0, 24, 0),
+@pytest.mark.parametrize("cfg,sched,L,iters,refresh,variant", [
+    ("c2", "bf16", 0, 16, 0, 0), ("c2", "fp32", 0, 16, 0, 0), ("c2", "fp64", 0, 16, 0, 0),
+    ("c2", "bf16", 8, 12, 0, 2), ("c3", "fp16", 8, 16, 4, 0), ("c3", "fp16", 8, 16, 4, 2), ("c3", "fp64", 0, 24, 0, 0),
 ])
-def test_full_size_sampled(cfg, sched, L, iters, refresh):
+def test_full_size_sampled(cfg, sched, L, iters, refresh, variant):
     import torch
 
     import paper_2504_09820_amd as fp
@@ -293,7 +303,7 @@ def test_full_size_sampled(cfg, sched, L, iters, refresh):
     Ht = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
     Yt = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
     st = torch.from_numpy(wl.sigma2).to(dev)
-    x, lab, fl = fp.detect(Ht, Yt, st, c["q"], iters, L, sched, refresh_every=refresh)
+    x, lab, fl = fp.detect(Ht, Yt, st, c["q"], iters, L, sched, refresh_every=refresh, variant=variant)
     torch.cuda.synchronize()
     x = x.cpu().numpy().astype(np.complex128)
     lab = lab.cpu().numpy().astype(np.int64)
@@ -302,7 +312,7 @@ def test_full_size_sampled(cfg, sched, L, iters, refresh):
     idx[-1] = c["B"] - 1
     sub = W.Workload(H=wl.H[idx], Y=wl.Y[idx], labels=wl.labels[idx], X=wl.X[idx], sigma2=wl.sigma2[idx],
                      q=c["q"], snr_db=wl.snr_db[idx])
-    spread, ref = oracle_spread(sub, c["q"], iters, L, sched, np.complex64, refresh=refresh)
+    spread, ref = oracle_spread(sub, c["q"], iters, L, sched, np.complex64, refresh=refresh, variant=variant)
     _spread_parity(x[idx], ref, spread, sched, f"full {cfg} {sched}", np.complex64)
     ok, n, bad = labels_consistent(lab[idx], ref.labels, x[idx], ref.xhat, c["q"])
     assert ok, (n, bad)

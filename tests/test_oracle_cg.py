@@ -524,3 +524,41 @@ def test_sequential_order_agrees_with_exact_order_when_well_conditioned():
     assert 0 < np.linalg.norm(r3.xhat - r4.xhat) / np.linalg.norm(r3.xhat) < 1e-5
     A, _ = D.gram(wl.H, wl.Y, wl.sigma2, D.schedule("fp32", accum="sequential"))
     assert np.array_equal(A, np.conj(np.swapaxes(A, -1, -2)))
+
+
+def test_split_form_matches_alg3_in_fp64():
+    """Left-preconditioned Alg. 3 and its symmetric form give the same iterates."""
+    for zeta, L in ((0.5, 4), (0.8, 8)):
+        wl = small_wl(B=5, Nbs=64, K=16, R=3, zeta=zeta)
+        r0 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 7, L, D.Schedule(variant=0))
+        r2 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 7, L, D.Schedule(variant=2))
+        assert np.linalg.norm(r0.xhat - r2.xhat) / np.linalg.norm(r0.xhat) < 1e-11
+
+
+def test_split_system_is_identity_on_diagonal_blocks_and_hermitian():
+    wl = small_wl(B=3, Nbs=64, K=16, R=1, zeta=0.7)
+    A, _ = D.gram(wl.H, wl.Y, wl.sigma2)
+    T, bad = D.bj_factor(A, 4)
+    assert not bad.any()
+    Ab = D.split_system(A, T)
+    assert np.array_equal(Ab, np.conj(np.swapaxes(Ab, -1, -2)))
+    for j in range(4):
+        sl = slice(4 * j, 4 * j + 4)
+        assert np.allclose(Ab[:, sl, sl], np.eye(4), atol=1e-12)
+    M, _ = D.bj_inverse(A, 4)
+    assert np.allclose(np.conj(np.swapaxes(T, -1, -2)) @ T, M, atol=1e-12)   # M_d = T^H T
+    # T is block lower triangular
+    for j in range(4):
+        sl = slice(4 * j, 4 * j + 4)
+        assert np.all(np.triu(T[:, sl, sl], 1) == 0)
+
+
+def test_split_form_refinement_and_low_precision():
+    wl = W.draw(6, 64, 16, 2, 16, 25.0, 0.6, 0.6, seed=31)
+    A, b = D.gram(wl.H, wl.Y, wl.sigma2)
+    xs = D.lmmse(A, b)
+    r = D.detect(wl.H, wl.Y, wl.sigma2, 16, 10, 4, D.schedule("fp16", variant=2, refine_steps=2))
+    assert np.linalg.norm(r.xhat - xs) / np.linalg.norm(xs) < 1e-5
+    r1 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 10, 4, D.schedule("fp16", variant=2, refresh_every=3))
+    r0 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 10, 4, D.schedule("fp16", variant=0, refresh_every=3))
+    assert np.linalg.norm(r1.xhat - xs) / np.linalg.norm(xs) < 2 * np.linalg.norm(r0.xhat - xs) / np.linalg.norm(xs) + 1e-4
