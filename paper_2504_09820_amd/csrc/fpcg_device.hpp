@@ -207,19 +207,48 @@ template <> struct Op<F8, 8> {
 };
 
 // ---------------------------------------------------------------------------
-// Column reductions over the four 16-lane groups of a wave.  Lanes l, l^16,
-// l^32, l^48 end with bitwise identical results (IEEE addition commutes).
+// Column reductions over the four 16-lane groups of a wave, on the VALU lane
+// swaps of gfx950: v_permlane16_swap exchanges 16-lane rows 0<->1 and 2<->3,
+// v_permlane32_swap the two 32-lane halves.  After each swap every lane holds
+// its own value and its partner's, so lanes l, l^16, l^32, l^48 end with
+// bitwise identical results ((v0 + v1) + (v2 + v3) in every lane).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void swap16(uint32_t v, uint32_t& a, uint32_t& b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    a = r[0]; b = r[1];
+}
+__device__ __forceinline__ void swap32(uint32_t v, uint32_t& a, uint32_t& b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    a = r[0]; b = r[1];
+}
+// both halves of the exchange for float / double: lo = value of the lower
+// row (or half) of the pair, hi = value of the upper one
+template <int S> __device__ __forceinline__ void pair_of(float v, float& lo, float& hi) {
+    uint32_t a, b;
+    if constexpr (S == 16) swap16(__float_as_uint(v), a, b); else swap32(__float_as_uint(v), a, b);
+    lo = __uint_as_float(a); hi = __uint_as_float(b);
+}
+template <int S> __device__ __forceinline__ void pair_of(double v, double& lo, double& hi) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    uint32_t a0, b0, a1, b1;
+    if constexpr (S == 16) { swap16((uint32_t)u, a0, b0); swap16((uint32_t)(u >> 32), a1, b1); }
+    else { swap32((uint32_t)u, a0, b0); swap32((uint32_t)(u >> 32), a1, b1); }
+    lo = __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0));
+    hi = __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
+}
 template <typename T> __device__ __forceinline__ T col_sum(T v) {
-    v = v + __shfl_xor(v, 16);
-    v = v + __shfl_xor(v, 32);
-    return v;
+    T lo, hi;
+    pair_of<16>(v, lo, hi);
+    v = lo + hi;
+    pair_of<32>(v, lo, hi);
+    return lo + hi;
 }
 template <typename T> __device__ __forceinline__ T col_max(T v) {
-    T o = __shfl_xor(v, 16);
-    v = v > o ? v : o;
-    o = __shfl_xor(v, 32);
-    return v > o ? v : o;
+    T lo, hi;
+    pair_of<16>(v, lo, hi);
+    v = lo > hi ? lo : hi;
+    pair_of<32>(v, lo, hi);
+    return lo > hi ? lo : hi;
 }
 template <typename T> __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll

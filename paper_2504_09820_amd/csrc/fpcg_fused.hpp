@@ -61,8 +61,9 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr int KPL = LOWP ? (SH % 8 == 0 ? 8 : 4) : 1;
     static constexpr int NKB = SH / KPL;              // contraction blocks per source wave
     static constexpr int F = KP / 16;                 // complex 16-column fragments of H
-    static constexpr int KPLG = LOWP ? 8 : 1;         // Gram contraction values per lane
-    static constexpr int KBG = 4 * KPLG;              // antennas per Gram contraction block
+    static constexpr int KPLG = LOWP ? 8 : 1;         // Gram contraction values per lane and MFMA
+    static constexpr int NSUB = LOWP ? 1 : (F <= 2 ? 8 : 4);   // Gram MFMAs per loaded block
+    static constexpr int KBG = 4 * KPLG * NSUB;       // antennas per loaded Gram block
     using O = Op<FMT, KPL>;
     using OG = Op<FMT, KPLG>;
     using Wt = typename O::work;
@@ -78,7 +79,10 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr int LDA = KP + 1;
     static constexpr int RC = 16;                     // antennas per refinement chunk
     static constexpr int NT = 64 * NW;
-    // LDS layout in bytes
+    // waves per SIMD the register allocation must allow without FP64
+    // refinement (1 = no constraint): three for one-wave K <= 32 channels
+    static constexpr int MIN_WAVES = (KP <= 32 && FMT != F64) ? 3 : 1;
+    // LDS layout in bytes: [Ar | Ai | Br | Bi | M | F | S | X | X64]
     static constexpr size_t W = sizeof(Wt);
     static constexpr size_t off_Ar = 0;
     static constexpr size_t off_Ai = off_Ar + W * KP * LDA;
@@ -86,25 +90,31 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr size_t off_Bi = off_Br + W * KP * 16;
     static constexpr size_t off_M = off_Bi + W * KP * 16;
     static constexpr size_t sz_M = LB ? 2 * W * KP * LB : 0;           // M_d or T blocks
-    static constexpr size_t off_X = off_M + sz_M;                       // x slots [2][SH][NT]
-    static constexpr size_t sz_X = 2 * W * SH * NT;
-    static constexpr size_t off_F = off_X + sz_X;                       // A operand fragments
+    static constexpr size_t off_F = off_M + sz_M;                       // A operand fragments
     static constexpr size_t sz_F = AFRAG_LDS ? (size_t)NAV * NT * sizeof(frag) : 0;
     static constexpr size_t off_S = off_F + sz_F;                       // scratch: BJ factors or exchange
-    static constexpr size_t sz_bj = LB ? 4 * W * KP * LB : 0;
+    // BJ setup scratch: T = C^{-1} for the left form before M = T^H T (the
+    // symmetric form writes T straight into M)
+    __host__ __device__ static constexpr size_t sz_bj(bool split) { return (LB && !split) ? 2 * W * KP * LB : 0; }
     static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * 8 : 0;    // p exchange (doubles)
-    static constexpr size_t sz_red = (size_t)2 * NW * 16 * 4 * 8;                    // dot partials, 2 parities
+    static constexpr size_t sz_red = (NW > 1) ? (size_t)2 * NW * 16 * 4 * 8 : 0;    // dot partials, 2 parities
     static constexpr size_t sz_ref = (NW > 1) ? (size_t)NW * RC * 16 * 2 * 8 : 0;   // refinement partials
     static constexpr size_t sz_ex = sz_xp + sz_red + sz_ref;
-    static constexpr size_t sz_S = sz_bj > sz_ex ? sz_bj : sz_ex;
-    static constexpr size_t lds_bytes = off_S + sz_S;                   // without refinement
-    static constexpr size_t off_X64 = lds_bytes;                        // FP64 iterate [2][SH][NT]
-    static constexpr size_t sz_X64 = 2 * 8 * (size_t)SH * NT;
-    static constexpr size_t lds_bytes_refine = off_X64 + sz_X64;
+    __host__ __device__ static constexpr size_t sz_S(bool split) { return sz_bj(split) > sz_ex ? sz_bj(split) : sz_ex; }
+    __host__ __device__ static constexpr size_t off_X(bool split) { return off_S + sz_S(split); }   // x slots [2][SH][NT]
+    static constexpr size_t sz_X = 2 * W * SH * NT;
+    static constexpr size_t sz_X64 = 2 * 8 * (size_t)SH * NT;           // FP64 iterate [2][SH][NT]
+    static_assert(sz_X <= 2 * W * KP * LDA, "x fits the Gram's slot");
+    // Once A sits in registers and no FP64 refresh reads the stored Gram, the
+    // Gram's LDS is dead after the operand is packed and x moves into it.
+    __host__ __device__ static constexpr bool x_in_gram(int refresh_every) { return AREG && refresh_every == 0; }
+    __host__ __device__ static constexpr size_t lds(bool split, bool refine, int refresh_every) {
+        return off_X(split) + (x_in_gram(refresh_every) ? 0 : sz_X) + (refine ? sz_X64 : 0);
+    }
 };
 
-template <int KP, int NW, int FMT, int LB, typename IOT>
-__global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
+template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1 : Cfg<KP, NW, FMT, LB>::MIN_WAVES))) void fused_kernel(const FusedParams P) {
     using C = Cfg<KP, NW, FMT, LB>;
     using O = typename C::O;
     using OG = typename C::OG;
@@ -123,10 +133,12 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     Wt* sBi = reinterpret_cast<Wt*>(smem + C::off_Bi);
     Wt* sMr = reinterpret_cast<Wt*>(smem + C::off_M);
     Wt* sMi = sMr + KP * (LB ? LB : 1);
-    Wt* sXr = reinterpret_cast<Wt*>(smem + C::off_X);                   // x, [SH][NT]
+    const bool x_in_gram = C::x_in_gram(P.refresh_every);
+    constexpr size_t off_X = C::off_X(LB > 0 && SPLIT);
+    Wt* sXr = reinterpret_cast<Wt*>(smem + (x_in_gram ? C::off_Ar : off_X));   // x, [SH][NT]
     Wt* sXi = sXr + SH * NT;
     frag* sF = reinterpret_cast<frag*>(smem + C::off_F);
-    double* sX64r = reinterpret_cast<double*>(smem + C::off_X64);      // refinement only
+    double* sX64r = reinterpret_cast<double*>(smem + off_X + (x_in_gram ? 0 : C::sz_X));   // refinement only
     double* sX64i = sX64r + SH * NT;
     unsigned char* scr = smem + C::off_S;
     double* sXP = reinterpret_cast<double*>(scr);                       // [NW][64][2*SH]
@@ -183,18 +195,27 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     // ------------------------------------------------------------ fp8 scales
     int eH = 0, eY = 0;
     if constexpr (FMT == F8) {
+        // eight range-checked loads in flight per lane (out of range reads zero)
         float mh = 0.f;
-        for (int i = tid; i < Nbs * K; i += NT) {
-            float re, im;
-            CxB<IOT>::load(bH, (uint32_t)i * ES, re, im);
-            mh = fmaxf(mh, fmaxf(fabsf(re), fabsf(im)));
+        const int nh = Nbs * K;
+        for (int i0 = 0; i0 < nh; i0 += 8 * NT) {
+            float re[8], im[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * NT + tid;
+                CxB<IOT>::load(bH, i < nh ? (uint32_t)i * ES : OOB, re[u], im[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) mh = fmaxf(mh, fmaxf(fabsf(re[u]), fabsf(im[u])));
         }
         mh = block_max(mh);
         float my = 0.f;
-        for (int a = g + 4 * wave; a < Nbs; a += 4 * NW) {
-            float re, im;
-            CxB<IOT>::load(bY, yofs(a), re, im);
-            my = fmaxf(my, fmaxf(fabsf(re), fabsf(im)));
+        for (int a0 = g + 4 * wave; a0 < Nbs; a0 += 32 * NW) {
+            float re[8], im[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) CxB<IOT>::load(bY, yofs(a0 + u * 4 * NW), re[u], im[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) my = fmaxf(my, fmaxf(fabsf(re[u]), fabsf(im[u])));
         }
         my = column_max(my);
         eH = fp8_scale_exp(mh);
@@ -210,47 +231,53 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
 #pragma unroll
         for (int s = 0; s < MFPW; ++s) { gBr[s] = acc_t{0, 0, 0, 0}; gBi[s] = acc_t{0, 0, 0, 0}; }
 
+        constexpr int NSUB = C::NSUB, NLD = KPLG * NSUB;
         for (int a0 = 0; a0 < Nbs; a0 += KBG) {
-            // range-checked loads (padding reads zero): all loads of the block in flight together
-            Wt hr[F][KPLG], hi[F][KPLG], yr[KPLG], yi[KPLG];
+            // range-checked loads (padding reads zero): all loads of the block in
+            // flight together; lane (g, n) takes antennas a0 + g NLD + j, j < NLD,
+            // the same for H and Y, so every MFMA contracts matching antennas
+            Wt hr[F][NLD], hi[F][NLD], yr[NLD], yi[NLD];
 #pragma unroll
-            for (int j = 0; j < KPLG; ++j) {
-                const int a = a0 + g * KPLG + j;
+            for (int j = 0; j < NLD; ++j) {
+                const int a = a0 + g * NLD + j;
 #pragma unroll
                 for (int f = 0; f < F; ++f) CxB<IOT>::load(bH, hofs(a, 16 * f + n), hr[f][j], hi[f][j]);
                 CxB<IOT>::load(bY, yofs(a), yr[j], yi[j]);
             }
-            gfrag Xr[F], Xi[F], nXi[F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                Xr[f] = OG::pack(hr[f], sH);
-                Xi[f] = OG::pack(hi[f], sH);
-                nXi[f] = OG::neg(Xi[f]);
-            }
-            const gfrag Yr = OG::pack(yr, sY), Yi = OG::pack(yi, sY);
-            int q = 0;
+            for (int u = 0; u < NSUB; ++u) {
+                gfrag Xr[F], Xi[F], nXi[F];
 #pragma unroll
-            for (int f1 = 0; f1 < F; ++f1) {
-#pragma unroll
-                for (int f2 = f1; f2 < F; ++f2) {
-                    if (NW == 1 || q % NW == wave) {
-                        const int s = q / NW;
-                        gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
-                        gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
-                        gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
-                        gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
-                    }
-                    ++q;
+                for (int f = 0; f < F; ++f) {
+                    Xr[f] = OG::pack(&hr[f][u * KPLG], sH);
+                    Xi[f] = OG::pack(&hi[f][u * KPLG], sH);
+                    nXi[f] = OG::neg(Xi[f]);
                 }
-            }
+                const gfrag Yr = OG::pack(&yr[u * KPLG], sY), Yi = OG::pack(&yi[u * KPLG], sY);
+                int q = 0;
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                if (NW == 1 || f % NW == wave) {
-                    const int s = f / NW;
-                    gBr[s] = OG::mfma(Xr[f], Yr, gBr[s]);
-                    gBr[s] = OG::mfma(Xi[f], Yi, gBr[s]);
-                    gBi[s] = OG::mfma(Xr[f], Yi, gBi[s]);
-                    gBi[s] = OG::mfma(nXi[f], Yr, gBi[s]);
+                for (int f1 = 0; f1 < F; ++f1) {
+#pragma unroll
+                    for (int f2 = f1; f2 < F; ++f2) {
+                        if (NW == 1 || q % NW == wave) {
+                            const int s = q / NW;
+                            gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
+                            gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
+                            gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
+                            gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
+                        }
+                        ++q;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    if (NW == 1 || f % NW == wave) {
+                        const int s = f / NW;
+                        gBr[s] = OG::mfma(Xr[f], Yr, gBr[s]);
+                        gBr[s] = OG::mfma(Xi[f], Yi, gBr[s]);
+                        gBi[s] = OG::mfma(Xr[f], Yi, gBi[s]);
+                        gBi[s] = OG::mfma(nXi[f], Yr, gBi[s]);
+                    }
                 }
             }
         }
@@ -307,90 +334,65 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     __syncthreads();
 
 
-    const bool split = (LB > 0) && (P.variant == 2);   // symmetric form of Alg. 3
-    const bool left = (LB > 0) && !split;             // Alg. 3 as printed / textbook PCG
+    constexpr bool split = (LB > 0) && SPLIT;          // symmetric form of Alg. 3
+    constexpr bool left = (LB > 0) && !SPLIT;          // Alg. 3 as printed / textbook PCG
 
     // ------------------------------------------------------------ 2. block-Jacobi setup (eq. pre_BJ)
     if constexpr (LB > 0) {
-        Wt* sLr = reinterpret_cast<Wt*>(scr);
-        Wt* sLi = sLr + KP * LB;
-        Wt* sTr = sLi + KP * LB;
+        Wt* sTr = reinterpret_cast<Wt*>(scr);         // T of the left form (then M = T^H T)
         Wt* sTi = sTr + KP * LB;
         const bool act = tid < KP;
         const int t = act ? tid : 0;
         const int i = t % LB, cb = t - i;             // row in block, first row of block
-        Wt ar[LB], ai[LB];
+        // Every lane of a block factors the whole block in registers (the same
+        // operations in the same order, so identical results): no exchange.
+        // Lower triangle of A_blk; the Cholesky factor C overwrites it, with
+        // 1 / c_jj kept in the (otherwise zero) imaginary slot of the diagonal.
+        Wt cr[LB][LB], ci[LB][LB];
+#pragma unroll
+        for (int r = 0; r < LB; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                cr[r][c] = sAr[(cb + r) * LDA + cb + c];
+                ci[r][c] = sAi[(cb + r) * LDA + cb + c];
+            }
+        Wt diag = 0;                                  // a_ii, for the not-PD fallback
+#pragma unroll
+        for (int r = 0; r < LB; ++r)
+            if (r == i) diag = cr[r][r];
+        bool blk_bad = false;
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
-            ar[j] = sAr[(cb + i) * LDA + cb + j];
-            ai[j] = sAi[(cb + i) * LDA + cb + j];
-        }
-        Wt diag = 0;
+            Wt d = cr[j][j];
+            if (!(d > 0) || !__builtin_isfinite(d)) { blk_bad = true; d = 1; }
+            const Wt l = sqrt(d), inv = (Wt)1 / l;
+            cr[j][j] = l;
+            ci[j][j] = inv;
 #pragma unroll
-        for (int j = 0; j < LB; ++j)
-            if (j == i) diag = ar[j];
-        bool bad = false;
-        // Cholesky A_blk = C C^H, C lower triangular, row i owned by this lane
+            for (int r = j + 1; r < LB; ++r) { cr[r][j] = cr[r][j] * inv; ci[r][j] = ci[r][j] * inv; }
 #pragma unroll
-        for (int j = 0; j < LB; ++j) {
-            if (act && i == j) {
-                Wt d = ar[j];
-                if (!(d > 0) || !__builtin_isfinite(d)) { bad = true; d = 1; }
-                sLr[(cb + j) * LB + j] = sqrt(d);
-                sLi[(cb + j) * LB + j] = 0;
-            }
-            __syncthreads();
-            const Wt ljj = sLr[(cb + j) * LB + j];
-            Wt lr = 0, li = 0;
-            if (act && i > j) {
-                lr = ar[j] / ljj;
-                li = ai[j] / ljj;
-                sLr[(cb + i) * LB + j] = lr;
-                sLi[(cb + i) * LB + j] = li;
-            }
-            __syncthreads();
-            if (act && i > j) {
+            for (int r = j + 1; r < LB; ++r)
 #pragma unroll
-                for (int k = j + 1; k < LB; ++k) {
-                    if (k <= i) {
-                        // a_ik -= l_ij conj(l_kj)
-                        const Wt kr = sLr[(cb + k) * LB + j], ki = sLi[(cb + k) * LB + j];
-                        ar[k] = ar[k] - (lr * kr + li * ki);
-                        ai[k] = ai[k] - (li * kr - lr * ki);
-                    }
+                for (int c = j + 1; c <= r; ++c) {
+                    // a_rc -= l_rj conj(l_cj)
+                    cr[r][c] = fma(-cr[r][j], cr[c][j], fma(-ci[r][j], ci[c][j], cr[r][c]));
+                    ci[r][c] = fma(-ci[r][j], cr[c][j], fma(cr[r][j], ci[c][j], ci[r][c]));
                 }
-            }
         }
-        // block-wide "not PD" decision: any row of the block failed
-        __syncthreads();
-        uint32_t* sBad = reinterpret_cast<uint32_t*>(sTr);   // temporary use before T is written
-        if (act && i == 0) sBad[cb / LB] = 0u;
-        __syncthreads();
-        if (act && bad) atomicOr(&sBad[cb / LB], 1u);
-        __syncthreads();
-        const bool blk_bad = act && sBad[cb / LB] != 0u;
-        __syncthreads();
-        // T = C^{-1}: this lane computes column i of T by forward substitution
+        // T = C^{-1}: this lane forms column i by forward substitution;
+        // t_m = 0 for m < i, so full-length sums add exact zeros
         Wt tr[LB], ti[LB];
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
-            tr[r] = 0; ti[r] = 0;
-            if (r == i) {
-                tr[r] = (Wt)1 / sLr[(cb + r) * LB + r];
-            } else if (r > i) {
-                Wt sr = 0, si = 0;
+            const Wt inv_rr = ci[r][r];
+            Wt sr = 0, si = 0;
 #pragma unroll
-                for (int m = 0; m < r; ++m) {
-                    if (m >= i) {
-                        const Wt cr = sLr[(cb + r) * LB + m], ci = sLi[(cb + r) * LB + m];
-                        sr = sr + (cr * tr[m] - ci * ti[m]);
-                        si = si + (cr * ti[m] + ci * tr[m]);
-                    }
-                }
-                const Wt crr = sLr[(cb + r) * LB + r];
-                tr[r] = -sr / crr;
-                ti[r] = -si / crr;
+            for (int m = 0; m < r; ++m) {
+                sr = fma(cr[r][m], tr[m], fma(-ci[r][m], ti[m], sr));
+                si = fma(cr[r][m], ti[m], fma(ci[r][m], tr[m], si));
             }
+            tr[r] = (r == i) ? inv_rr : (r > i ? -sr * inv_rr : (Wt)0);
+            ti[r] = (r > i) ? -si * inv_rr : (Wt)0;
         }
         if (blk_bad) {
             // not positive definite: T = diag(a_ii)^{-1/2}, so M_d = diag(a_ii)^{-1}
@@ -411,20 +413,19 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
         }
         __syncthreads();
-        if (!split) {
+        if constexpr (!split) {
             // M = T^H T: row i
+            // with column i of T in this lane's registers; T is lower triangular
+            // with zeros stored above the diagonal, so full-length sums add exact zeros
             if (act) {
 #pragma unroll
                 for (int j = 0; j < LB; ++j) {
                     Wt mr = 0, mi = 0;
 #pragma unroll
                     for (int m = 0; m < LB; ++m) {
-                        if (m >= i && m >= j) {
-                            const Wt ar_ = sTr[(cb + m) * LB + i], ai_ = sTi[(cb + m) * LB + i];   // T[m][i]
-                            const Wt br_ = sTr[(cb + m) * LB + j], bi_ = sTi[(cb + m) * LB + j];   // T[m][j]
-                            mr = mr + (ar_ * br_ + ai_ * bi_);
-                            mi = mi + (ar_ * bi_ - ai_ * br_);
-                        }
+                        const Wt br_ = sTr[(cb + m) * LB + j], bi_ = sTi[(cb + m) * LB + j];   // T[m][j]
+                        mr = fma(tr[m], br_, fma(ti[m], bi_, mr));                           // conj(T[m][i]) T[m][j]
+                        mi = fma(tr[m], bi_, fma(-ti[m], br_, mi));
                     }
                     sMr[(cb + i) * LB + j] = mr;
                     sMi[(cb + i) * LB + j] = mi;
@@ -432,68 +433,99 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             }
             __syncthreads();
         } else {
-            // A <- T A T^H in place: W = A T^H row by row (thread = row), then
-            // T W column by column (thread = column); T is block lower triangular
-            if (act) {
-                const int m = tid;
-#pragma unroll 1
-                for (int c0 = 0; c0 < KP; c0 += LB) {
-                    Wt a_r[LB], a_i[LB];
+            // A <- T A T^H in place, upper triangle only (the lower one is read as
+            // its conjugate, the diagonal as real: the result is Hermitian by
+            // construction).  T is block lower triangular, so
+            //   W = A T^H:   W[m][bL + c] = sum_{j <= c} A[m][bL + j] conj(T[bL + c][bL + j])
+            //   A = T W:     A[bL + r][n] = sum_{j <= r} T[bL + r][bL + j] W[bL + j][n]
+            // Items (row m or column n, block b) are independent and update only
+            // their own L-segment.  Each lane keeps one block b of T in registers
+            // and takes the items of that block (rows, then columns, strided);
+            // loads are unconditional, stores guarded to what the upper triangle needs.
+            constexpr int NB = KP / LB, RPL = NT / NB, NIT = KP / RPL;
+            static_assert(NT % NB == 0 && KP % RPL == 0, "lanes split evenly over the blocks");
+            const int b = tid % NB, q = tid / NB;
+            // the block of T in registers for L <= 4; for larger blocks it is read
+            // from LDS next to each item's loads (register budget)
+            constexpr bool TREG = LB <= 4;
+            Wt Tr_[TREG ? LB : 1][TREG ? LB : 1], Ti_[TREG ? LB : 1][TREG ? LB : 1];
+            if constexpr (TREG) {
 #pragma unroll
-                    for (int j = 0; j < LB; ++j) { a_r[j] = sAr[m * LDA + c0 + j]; a_i[j] = sAi[m * LDA + c0 + j]; }
+                for (int r = 0; r < LB; ++r)
 #pragma unroll
-                    for (int c = 0; c < LB; ++c) {
-                        Wt wr = 0, wi = 0;
+                    for (int j = 0; j <= r; ++j) { Tr_[r][j] = sMr[(b * LB + r) * LB + j]; Ti_[r][j] = sMi[(b * LB + r) * LB + j]; }
+            }
+            auto Tr = [&](int r, int j) -> Wt { if constexpr (TREG) return Tr_[r][j]; else return sMr[(b * LB + r) * LB + j]; };
+            auto Ti = [&](int r, int j) -> Wt { if constexpr (TREG) return Ti_[r][j]; else return sMi[(b * LB + r) * LB + j]; };
 #pragma unroll
-                        for (int j = 0; j <= c; ++j) {          // w += a_j conj(T[c][j])
-                            const Wt t_r = sMr[(c0 + c) * LB + j], t_i = sMi[(c0 + c) * LB + j];
-                            wr = fma(a_r[j], t_r, wr);
-                            wr = fma(a_i[j], t_i, wr);
-                            wi = fma(a_i[j], t_r, wi);
-                            wi = fma(-a_r[j], t_i, wi);
-                        }
-                        sAr[m * LDA + c0 + c] = wr;
-                        sAi[m * LDA + c0 + c] = wi;
+            for (int it = 0; it < NIT; ++it) {
+                const int m = q + it * RPL;
+                Wt a_r[LB], a_i[LB];
+#pragma unroll
+                for (int j = 0; j < LB; ++j) { a_r[j] = sAr[m * LDA + b * LB + j]; a_i[j] = sAi[m * LDA + b * LB + j]; }
+                Wt w_r[LB], w_i[LB];
+#pragma unroll
+                for (int c = 0; c < LB; ++c) {
+                    Wt wr = 0, wi = 0;
+#pragma unroll
+                    for (int j = 0; j <= c; ++j) {          // w += a_j conj(T[c][j])
+                        wr = fma(a_r[j], Tr(c, j), wr);
+                        wr = fma(a_i[j], Ti(c, j), wr);
+                        wi = fma(a_i[j], Tr(c, j), wi);
+                        wi = fma(-a_r[j], Ti(c, j), wi);
                     }
+                    w_r[c] = wr;
+                    w_i[c] = wi;
+                }
+                if (m / LB <= b) {                          // rows the upper triangle needs
+#pragma unroll
+                    for (int c = 0; c < LB; ++c) { sAr[m * LDA + b * LB + c] = w_r[c]; sAi[m * LDA + b * LB + c] = w_i[c]; }
                 }
             }
             __syncthreads();
-            if (act) {
-                const int c = tid;
-#pragma unroll 1
-                for (int r0 = 0; r0 < KP; r0 += LB) {
-                    Wt w_r[LB], w_i[LB];
 #pragma unroll
-                    for (int j = 0; j < LB; ++j) { w_r[j] = sAr[(r0 + j) * LDA + c]; w_i[j] = sAi[(r0 + j) * LDA + c]; }
+            for (int it = 0; it < NIT; ++it) {
+                const int nn = q + it * RPL;
+                Wt w_r[LB], w_i[LB];
 #pragma unroll
-                    for (int r = 0; r < LB; ++r) {
-                        Wt vr = 0, vi = 0;
+                for (int j = 0; j < LB; ++j) { w_r[j] = sAr[(b * LB + j) * LDA + nn]; w_i[j] = sAi[(b * LB + j) * LDA + nn]; }
+                Wt v_r[LB], v_i[LB];
 #pragma unroll
-                        for (int j = 0; j <= r; ++j) {          // v += T[r][j] w_j
-                            const Wt t_r = sMr[(r0 + r) * LB + j], t_i = sMi[(r0 + r) * LB + j];
-                            vr = fma(t_r, w_r[j], vr);
-                            vr = fma(-t_i, w_i[j], vr);
-                            vi = fma(t_r, w_i[j], vi);
-                            vi = fma(t_i, w_r[j], vi);
-                        }
-                        sAr[(r0 + r) * LDA + c] = vr;
-                        sAi[(r0 + r) * LDA + c] = vi;
+                for (int r = 0; r < LB; ++r) {
+                    Wt vr = 0, vi = 0;
+#pragma unroll
+                    for (int j = 0; j <= r; ++j) {          // v += T[r][j] w_j
+                        vr = fma(Tr(r, j), w_r[j], vr);
+                        vr = fma(-Ti(r, j), w_i[j], vr);
+                        vi = fma(Tr(r, j), w_i[j], vi);
+                        vi = fma(Ti(r, j), w_r[j], vi);
                     }
+                    v_r[r] = vr;
+                    v_i[r] = vi;
                 }
-            }
-            __syncthreads();
-            // exactly Hermitian: lower triangle = conjugate of the upper one, real diagonal
-            if (act) {
-                const int r = tid;
-                for (int c = 0; c < r; ++c) {
-                    sAr[r * LDA + c] = sAr[c * LDA + r];
-                    sAi[r * LDA + c] = -sAi[c * LDA + r];
+                if (b * LB <= nn) {                         // blocks of rows that reach the upper triangle
+#pragma unroll
+                    for (int r = 0; r < LB; ++r) { sAr[(b * LB + r) * LDA + nn] = v_r[r]; sAi[(b * LB + r) * LDA + nn] = v_i[r]; }
                 }
-                sAi[r * LDA + r] = 0;
             }
             __syncthreads();
         }
     }
+
+    // element (r, c) of the u_W matrix of the iteration: the Gram (stored whole),
+    // or T A T^H (stored as its upper triangle; Hermitian with real diagonal)
+    auto a_at = [&](int r, int c, Wt& re, Wt& im) {
+        if constexpr (split) {
+            const bool up = r <= c;
+            const int o = up ? r * LDA + c : c * LDA + r;
+            const Wt v = sAi[o];
+            re = sAr[o];
+            im = (r == c) ? (Wt)0 : (up ? v : -v);
+        } else {
+            re = sAr[r * LDA + c];
+            im = sAi[r * LDA + c];
+        }
+    };
 
     // ------------------------------------------------------------ fp8 scale of the u_MV matrix
     int eA = 0;
@@ -501,7 +533,9 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
         float ma = 0.f;
         for (int i = tid; i < K * K; i += NT) {
             const int r = i / K, c = i % K;
-            ma = fmaxf(ma, fmaxf(fabsf((float)sAr[r * LDA + c]), fabsf((float)sAi[r * LDA + c])));
+            Wt re, im;
+            a_at(r, c, re, im);
+            ma = fmaxf(ma, fmaxf(fabsf((float)re), fabsf((float)im)));
         }
         ma = block_max(ma);
         eA = fp8_scale_exp(ma);
@@ -535,10 +569,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                     Wt vr[KPL], vi[KPL];
                     const int rr_ = rowc(phi);
 #pragma unroll
-                    for (int j = 0; j < KPL; ++j) {
-                        vr[j] = sAr[rr_ * LDA + colc(ws, kb, j)];
-                        vi[j] = sAi[rr_ * LDA + colc(ws, kb, j)];
-                    }
+                    for (int j = 0; j < KPL; ++j) a_at(rr_, colc(ws, kb, j), vr[j], vi[j]);
                     const frag fr = O::pack(vr, sA), fi = O::pack(vi, sA);
                     if constexpr (C::AREG) {
                         afr[fidx(phi, ws, kb, 0)] = fr;
@@ -549,14 +580,18 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                     }
                 }
     }
+    if constexpr (NW > 1) {
+        if (x_in_gram) __syncthreads();               // every wave has packed before x overwrites the Gram
+    }
     auto A_op = [&](int phi, int ws, int kb, int ri) -> frag {
         if constexpr (C::AREG) {
             return afr[fidx(phi, ws, kb, ri)];
         } else if constexpr (C::AFRAG_LDS) {
             return sF[fidx(phi, ws, kb, ri) * NT + tid];
         } else {
-            const Wt* src = ri ? sAi : sAr;
-            Wt v = src[rowc(phi) * LDA + colc(ws, kb, 0)];
+            Wt re, im;
+            a_at(rowc(phi), colc(ws, kb, 0), re, im);
+            const Wt v = ri ? im : re;
             return O::pack(&v, 1.f);
         }
     };
@@ -680,7 +715,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
         }
     };
 
-    const int passes = 1 + P.refine_steps;
+    const int passes = REF ? 1 + P.refine_steps : 1;   // REF: built with FP64 refinement
     int es = 0;                                       // exponent of the current pass's residual scale
     for (int pass = 0; pass < passes; ++pass) {
         if (pass > 0) {
@@ -804,7 +839,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             const double sc = ldexp(1.0, -es);
 #pragma unroll
             for (int e = 0; e < SH; ++e) { resr[e] *= sc; resi[e] *= sc; }
-            if (split) apply_T(resr, resi);             // b_bar = T (r sc), FP64 arithmetic
+            if constexpr (split) apply_T(resr, resi);   // b_bar = T (r sc), FP64 arithmetic
 #pragma unroll
             for (int e = 0; e < SH; ++e) {
                 const int c = base_c + e;
@@ -825,13 +860,12 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                 rr[e] = sBr[(base_c + e) * 16 + n];
                 ri[e] = sBi[(base_c + e) * 16 + n];
             }
-            if (split && pass == 0) apply_T(rr, ri);     // b_bar = T b
             if (split && pass == 0) {
-                // keep b_bar for the FP64 refresh
+                apply_T(rr, ri);                        // b_bar = T b, kept for the FP64 refresh
 #pragma unroll
                 for (int e = 0; e < SH; ++e) { sBr[(base_c + e) * 16 + n] = rr[e]; sBi[(base_c + e) * 16 + n] = ri[e]; }
             }
-            if (left) apply_M(rr, ri, wr, wi);         // p0 = M r0 (Alg. 3) or r0
+            if constexpr (left) apply_M(rr, ri, wr, wi);   // p0 = M r0 (Alg. 3) or r0
             else {
 #pragma unroll
                 for (int e = 0; e < SH; ++e) { wr[e] = rr[e]; wi[e] = ri[e]; }
@@ -903,14 +937,19 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             // ---- phi = p^H varpi, rho_{i-1}  [u_IP]
             Wt v[4];
             v[0] = 0; v[1] = 0;
+            const bool need_rp = left && (P.variant == 0);
 #pragma unroll
             for (int e = 0; e < SH; ++e) {
                 v[0] = fma(pr[e], wr[e], v[0]);
                 v[0] = fma(pi[e], wi[e], v[0]);
-                v[1] = fma(rr[e], pr[e], v[1]);
-                v[1] = fma(ri[e], pi[e], v[1]);
             }
-            const bool need_rp = left && (P.variant == 0);
+            if (need_rp) {
+#pragma unroll
+                for (int e = 0; e < SH; ++e) {
+                    v[1] = fma(rr[e], pr[e], v[1]);
+                    v[1] = fma(ri[e], pi[e], v[1]);
+                }
+            }
             col_reduce(v, need_rp ? 2 : 1);
             const Wt ph = v[0];
             const Wt rho_prev = need_rp ? v[1] : rho_cur;
@@ -943,8 +982,9 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
                         const int cc = (g * NW + ws) * SH + kb;
 #pragma unroll
                         for (int phi = 0; phi < NF; ++phi) {
-                            const double a_r = (double)sAr[rowc64(phi) * LDA + cc];
-                            const double a_i = (double)sAi[rowc64(phi) * LDA + cc];
+                            Wt are, aim;
+                            a_at(rowc64(phi), cc, are, aim);
+                            const double a_r = (double)are, a_i = (double)aim;
                             Rr[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, bx, Rr[phi], 0, 0, 0);
                             Rr[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i, by, Rr[phi], 0, 0, 0);
                             Ri[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, bx, Ri[phi], 0, 0, 0);
@@ -968,7 +1008,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             }
             // ---- z = M r (left form) or r, rho_i, beta, p
             Wt zr[SH], zi[SH];
-            if (left) apply_M(rr, ri, zr, zi);
+            if constexpr (left) apply_M(rr, ri, zr, zi);
             else {
 #pragma unroll
                 for (int e = 0; e < SH; ++e) { zr[e] = rr[e]; zi[e] = ri[e]; }
@@ -994,8 +1034,8 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             Wt xo_r[SH], xo_i[SH];
 #pragma unroll
             for (int e = 0; e < SH; ++e) { xo_r[e] = sXr[e * NT + tid]; xo_i[e] = sXi[e * NT + tid]; }
-            if (split) apply_TH(xo_r, xo_i);           // x = T^H x_bar  (u_W)
-            if (P.refine_steps > 0) {
+            if constexpr (split) apply_TH(xo_r, xo_i);  // x = T^H x_bar  (u_W)
+            if (REF && P.refine_steps > 0) {
 #pragma unroll
                 for (int e = 0; e < SH; ++e) { sX64r[e * NT + tid] = (double)xo_r[e]; sX64i[e * NT + tid] = (double)xo_i[e]; }
             } else if (colv) {
@@ -1015,7 +1055,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
             double dr[SH], di[SH];
 #pragma unroll
             for (int e = 0; e < SH; ++e) { dr[e] = (double)sXr[e * NT + tid]; di[e] = (double)sXi[e * NT + tid]; }
-            if (split) apply_TH(dr, di);               // d = T^H d_bar  (FP64 arithmetic)
+            if constexpr (split) apply_TH(dr, di);      // d = T^H d_bar  (FP64 arithmetic)
             const double us = ldexp(1.0, es);          // x += d / sc, exact scaling
 #pragma unroll
             for (int e = 0; e < SH; ++e) {
@@ -1027,7 +1067,7 @@ __global__ __launch_bounds__(64 * NW) void fused_kernel(const FusedParams P) {
     }
 
     // ------------------------------------------------------------ 5. slicer + stores (refined, FP64)
-    if (colv && P.refine_steps > 0) {
+    if (REF && colv && P.refine_steps > 0) {
         const double nu = P.nu, mm = (double)P.m;
 #pragma unroll
         for (int e = 0; e < SH; ++e) {

@@ -99,6 +99,12 @@ fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
     const int fmt = s->mv_op;
     const int kp = pick_kp(K, fmt, L);
     if (!kp) return fail(FPCG_E_UNSUPPORTED, "no variant for K=%d fmt=%d L=%d", K, fmt, L);
+    {
+        const KernelEntry* e = find_entry(kp, fmt, L, 1);   // the layout does not depend on the I/O type
+        const size_t lds = e->lds(L > 0 && s->variant == 2, s->refine_steps > 0, s->refresh_every);
+        if (lds > 160 * 1024)
+            return fail(FPCG_E_UNSUPPORTED, "this schedule at K=%d needs %zu bytes of LDS (160 KiB per workgroup)", K, lds);
+    }
     if (plan) {
         plan->KP = kp;
         plan->FMT = fmt;
@@ -140,8 +146,11 @@ fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int6
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         for (const auto& t : table())
-            if (t.lds_refine > 65536)
-                (void)hipFuncSetAttribute(t.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.lds_refine);
+            for (int sp = 0; sp < 2; ++sp)
+                for (int r = 0; r < 2; ++r)
+                    if (t.lds(sp != 0, r != 0, 1) > 65536)   // the largest layout of that build
+                        (void)hipFuncSetAttribute(t.fn[sp][r], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)t.lds(sp != 0, r != 0, 1));
     });
     (void)device;
     if (flags && R > 16) {   // several workgroups per channel OR their flags together
@@ -158,7 +167,10 @@ fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int6
     while ((1 << p.bits) < p.m) ++p.bits;
     p.nu = std::sqrt(2.0 * (qam - 1) / 3.0);
     dim3 grid((unsigned)B, (unsigned)((R + 15) / 16));
-    e->launch(p, grid, plan.sched.refine_steps > 0 ? e->lds_refine : e->lds, stream);
+    const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
+    const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
+    const size_t lds = e->lds(sp != 0, ref != 0, p.refresh_every);   // within 160 KiB (check_args)
+    e->launch[sp][ref](p, grid, lds, stream);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(FPCG_E_DEVICE, "fused kernel launch: %s", hipGetErrorString(err));
     return FPCG_OK;

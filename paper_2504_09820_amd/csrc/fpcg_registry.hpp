@@ -11,9 +11,10 @@ namespace fpcg {
 
 struct KernelEntry {
     int KP, NW, FMT, LB, io_c64;
-    size_t lds, lds_refine;     // dynamic LDS without / with FP64 refinement
-    const void* fn;
-    void (*launch)(const FusedParams&, dim3, size_t, hipStream_t);
+    size_t (*lds)(bool split, bool refine, int refresh_every);   // dynamic LDS bytes of a launch
+    // builds of the kernel: [symmetric block-Jacobi form][FP64 refinement]
+    const void* fn[2][2];
+    void (*launch[2][2])(const FusedParams&, dim3, size_t, hipStream_t);
 };
 
 void register_f64(std::vector<KernelEntry>& v);
@@ -27,22 +28,36 @@ void register_f8(std::vector<KernelEntry>& v);
 // would not fit the register file
 constexpr int waves_for(int KP, int FMT) { return (FMT == F64 && KP >= 64) ? 2 : 1; }
 
-#define FPCG_ENTRY(KP_, FMT_, LB_, IOT_)                                                          \
-    do {                                                                                          \
-        constexpr int NW_ = waves_for(KP_, FMT_);                                                       \
-        using C_ = Cfg<KP_, NW_, FMT_, LB_>;                                                      \
-        KernelEntry e;                                                                            \
-        e.KP = KP_; e.NW = NW_; e.FMT = FMT_; e.LB = LB_;                                         \
-        e.io_c64 = sizeof(IOT_) == 4 ? 1 : 0;                                                     \
-        e.lds = C_::lds_bytes;                                                                    \
-        e.lds_refine = C_::lds_bytes_refine;                                                      \
-        e.fn = reinterpret_cast<const void*>(&fused_kernel<KP_, NW_, FMT_, LB_, IOT_>);           \
-        e.launch = [](const FusedParams& p, dim3 grid, size_t lds, hipStream_t s) {               \
-            hipLaunchKernelGGL((fused_kernel<KP_, NW_, FMT_, LB_, IOT_>), grid, dim3(64 * NW_),   \
-                               lds, s, p);                                                        \
-        };                                                                                        \
-        v.push_back(e);                                                                           \
-    } while (0)
+template <int KP, int NW, int FMT, int LB, bool SP, bool RF, typename IOT>
+void set_build(KernelEntry& e) {
+    e.fn[SP][RF] = reinterpret_cast<const void*>(&fused_kernel<KP, NW, FMT, LB, SP, RF, IOT>);
+    e.launch[SP][RF] = [](const FusedParams& p, dim3 grid, size_t lds, hipStream_t s) {
+        hipLaunchKernelGGL((fused_kernel<KP, NW, FMT, LB, SP, RF, IOT>), grid, dim3(64 * NW), lds, s, p);
+    };
+}
+
+// LB = 0 builds only the plain form (the symmetric slot repeats it)
+template <int KP, int FMT, int LB, typename IOT>
+void add_entry(std::vector<KernelEntry>& v) {
+    constexpr int NW = waves_for(KP, FMT);
+    using C = Cfg<KP, NW, FMT, LB>;
+    KernelEntry e;
+    e.KP = KP; e.NW = NW; e.FMT = FMT; e.LB = LB;
+    e.io_c64 = sizeof(IOT) == 4 ? 1 : 0;
+    e.lds = [](bool sp, bool r, int f) -> size_t { return C::lds(LB > 0 && sp, r, f); };
+    set_build<KP, NW, FMT, LB, false, false, IOT>(e);
+    set_build<KP, NW, FMT, LB, false, true, IOT>(e);
+    if constexpr (LB > 0) {
+        set_build<KP, NW, FMT, LB, true, false, IOT>(e);
+        set_build<KP, NW, FMT, LB, true, true, IOT>(e);
+    } else {
+        e.fn[1][0] = e.fn[0][0]; e.fn[1][1] = e.fn[0][1];
+        e.launch[1][0] = e.launch[0][0]; e.launch[1][1] = e.launch[0][1];
+    }
+    v.push_back(e);
+}
+
+#define FPCG_ENTRY(KP_, FMT_, LB_, IOT_) add_entry<KP_, FMT_, LB_, IOT_>(v)
 
 #define FPCG_ENTRIES_IO(KP_, FMT_, LB_) \
     FPCG_ENTRY(KP_, FMT_, LB_, float);  \
