@@ -193,7 +193,8 @@ fpcg_status fpcg_poll(fpcg_server* srv, uint64_t ticket, int32_t* done);
 /* Advance until every submitted request has completed. */
 fpcg_status fpcg_drain(fpcg_server* srv);
 
-/* In-flight requests, queued requests and device bytes held right now. */
+/* In-flight requests, queued requests, and device bytes of the server's slot
+ * buffers (kept for reuse between requests; never above the budget). */
 fpcg_status fpcg_server_stats(fpcg_server* srv, int32_t* in_flight, int32_t* queued, size_t* bytes_held);
 
 /* Drains, then frees the server. */

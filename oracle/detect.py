@@ -22,13 +22,13 @@ What is computed and where the paper defines it
                    refresh, optional FP64 iterative refinement through H,
                    then the QAM slicer.
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
   R-alpha  alpha and beta use the real parts of the inner products (A is
            Hermitian positive definite, the imaginary parts are rounding noise).
   R-guard  breakdown: if phi <= 0, rho <= 0 or either is not finite, that
            column is frozen from then on (alpha = beta = 0, x unchanged) and
            its channel is flagged.
-  R-sched  the build's schedules: operands rounded to the operand format,
+  R-sched  the reduced-precision schedules: operands rounded to the operand format,
            products exact, each matrix product / inner product summed exactly
            and rounded once to the accumulation format (an idealised matrix
            core); u_W updates x, r, p use one rounding per fused multiply-add.

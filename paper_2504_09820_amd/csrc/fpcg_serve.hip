@@ -69,7 +69,7 @@ struct fpcg_server {
     std::vector<Slot> slots;
     std::deque<Req*> queue;
     std::unordered_map<uint64_t, Req*> reqs;
-    size_t held = 0;   // device bytes of the slot buffers in use
+    size_t held = 0;   // device bytes of all slot buffers
     uint64_t next = 1;
     std::mutex mu;
 };
@@ -92,31 +92,50 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
             if (rq->r.flags) std::memcpy(rq->r.flags, hb + L.fl, (size_t)rq->r.B * 4);
         }
         rq->state = 2;
-        s->held -= rq->bytes;
         sl.req = nullptr;
     }
-    // admit in arrival order while a slot is free and the budget allows
+    // admit in arrival order while a slot is free and the budget allows; the
+    // budget covers every device buffer the server holds (slot buffers are
+    // kept and reused, and grown only when a request needs more)
     while (!s->queue.empty()) {
         Req* rq = s->queue.front();
-        if (s->held + rq->bytes > s->ctx->budget) break;
-        Slot* free_slot = nullptr;
-        for (Slot& sl : s->slots)
-            if (!sl.req) { free_slot = &sl; break; }
-        if (!free_slot) break;
-        s->queue.pop_front();
-        Slot& sl = *free_slot;
         const Layout L = layout_of(rq->r);
-        if (sl.dcap < L.total) {
-            if (sl.dbuf) (void)hipFree(sl.dbuf);
-            if (sl.hbuf) (void)hipHostFree(sl.hbuf);
-            sl.dbuf = nullptr; sl.hbuf = nullptr; sl.dcap = sl.hcap = 0;
-            if (hipMalloc(&sl.dbuf, L.total) != hipSuccess || hipHostMalloc(&sl.hbuf, L.total, hipHostMallocDefault) != hipSuccess) {
+        Slot* pick = nullptr;
+        for (Slot& sl : s->slots)   // a free slot that already fits: no allocation
+            if (!sl.req && sl.dcap >= L.total) { pick = &sl; break; }
+        if (!pick) {
+            for (Slot& sl : s->slots)
+                if (!sl.req) { pick = &sl; break; }
+            if (!pick) break;                                      // every slot busy
+            if (s->held - pick->dcap + L.total > s->ctx->budget) {
+                // release the buffers of the other idle slots, then try again
+                for (Slot& sl : s->slots) {
+                    if (sl.req || &sl == pick || !sl.dbuf) continue;
+                    (void)hipFree(sl.dbuf);
+                    (void)hipHostFree(sl.hbuf);
+                    s->held -= sl.dcap;
+                    sl.dbuf = nullptr; sl.hbuf = nullptr; sl.dcap = sl.hcap = 0;
+                }
+                if (s->held - pick->dcap + L.total > s->ctx->budget) break;   // wait for running requests
+            }
+            if (pick->dbuf) (void)hipFree(pick->dbuf);
+            if (pick->hbuf) (void)hipHostFree(pick->hbuf);
+            s->held -= pick->dcap;
+            pick->dbuf = nullptr; pick->hbuf = nullptr; pick->dcap = pick->hcap = 0;
+            if (hipMalloc(&pick->dbuf, L.total) != hipSuccess ||
+                hipHostMalloc(&pick->hbuf, L.total, hipHostMallocDefault) != hipSuccess) {
+                if (pick->dbuf) (void)hipFree(pick->dbuf);
+                pick->dbuf = nullptr; pick->hbuf = nullptr;
+                s->queue.pop_front();
                 rq->status = fail(FPCG_E_NOMEM, "device/pinned allocation of %zu bytes failed", L.total);
                 rq->state = 2;
                 continue;
             }
-            sl.dcap = sl.hcap = L.total;
+            pick->dcap = pick->hcap = L.total;
+            s->held += L.total;
         }
+        s->queue.pop_front();
+        Slot& sl = *pick;
         char* hb = static_cast<char*>(sl.hbuf);
         char* db = static_cast<char*>(sl.dbuf);
         const fpcg_request& r = rq->r;
@@ -148,7 +167,6 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
         }
         rq->state = 1;
         sl.req = rq;
-        s->held += rq->bytes;
     }
     return FPCG_OK;
 }

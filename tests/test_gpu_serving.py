@@ -1,0 +1,114 @@
+"""Continuous-batching request loop (fpcg_server_*): requests of mixed shapes
+and schedules submitted together run overlapped on the device, and every
+request's result is bitwise the one the same request gives alone (each
+channel is computed by its own workgroup in a fixed order)."""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+SHAPES = [(64, 8), (64, 16), (64, 32), (128, 8), (128, 16), (128, 32), (128, 64), (256, 16), (256, 32), (256, 64)]
+SCHEDS = [("fp16", 4, 2, 0), ("fp32", 0, 0, 0), ("bf16", 8, 2, 0), ("fp64", 0, 0, 0), ("fp16", 8, 0, 4), ("fp8", 4, 2, 0)]
+
+
+def _requests(n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        Nbs, K = SHAPES[rng.integers(len(SHAPES))]
+        sched, L, v, refresh = SCHEDS[rng.integers(len(SCHEDS))]
+        if L and K % L:
+            L = 4
+        if sched == "fp8" and K < 32:
+            sched = "fp16"
+        B = int(rng.integers(1, 120))
+        q = int(rng.choice([16, 64]))
+        wl = W.draw(B, Nbs, K, 14, q, float(rng.uniform(5, 25)), float(rng.uniform(0, 0.9)),
+                    float(rng.uniform(0, 0.9)), seed=1000 + i)
+        io = np.complex128 if sched == "fp64" else np.complex64
+        reqs.append(dict(H=wl.H.astype(io), Y=wl.Y.astype(io), s2=wl.sigma2, q=q, iters=int(rng.integers(4, 17)), L=L,
+                         sched=sched, variant=v, refresh=refresh))
+    return reqs
+
+
+def _alone(fp, r):
+    import torch
+
+    dev = torch.device("cuda:0")
+    x, lab, fl = fp.detect(torch.from_numpy(r["H"]).to(dev), torch.from_numpy(r["Y"]).to(dev),
+                           torch.from_numpy(r["s2"]).to(dev), r["q"], r["iters"], r["L"], r["sched"],
+                           refresh_every=r["refresh"], variant=r["variant"])
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), lab.cpu().numpy(), fl.cpu().numpy().astype(np.uint32)
+
+
+def _serve(fp, reqs, budget, n_slots):
+    ctx = fp.Context(0, budget)
+    srv = fp.Server(ctx, n_slots=n_slots, queue_cap=len(reqs))
+    tickets = [srv.submit(r["H"], r["Y"], r["s2"], r["q"], r["iters"], r["L"], r["sched"],
+                          refresh_every=r["refresh"], variant=r["variant"]) for r in reqs]
+    out = {}
+    max_flight, max_held = 0, 0
+    t0 = time.time()
+    while len(out) < len(tickets):
+        fl_, q_, held = srv.stats()
+        max_flight, max_held = max(max_flight, fl_), max(max_held, held)
+        for t in tickets:
+            if t not in out:
+                res = srv.poll(t)
+                if res is not None:
+                    out[t] = res
+        assert time.time() - t0 < 60, "serving did not finish"
+    srv.close()
+    ctx.close()
+    return [out[t] for t in tickets], max_flight, max_held
+
+
+def _check_same(reqs, alone, served):
+    for i, (r, a, s) in enumerate(zip(reqs, alone, served)):
+        assert np.array_equal(a[0].view(np.uint8), s[0].view(np.uint8)), f"request {i} x_hat differs"
+        assert np.array_equal(a[1], s[1]), f"request {i} labels differ"
+        assert np.array_equal(a[2], s[2]), f"request {i} flags differ"
+
+
+def test_mixed_requests_match_alone_bitwise():
+    import paper_2504_09820_amd as fp
+
+    reqs = _requests(14, 7)
+    _say("case serving: 14 mixed requests, 4 slots, default budget")
+    alone = [_alone(fp, r) for r in reqs]
+    served, max_flight, _ = _serve(fp, reqs, 0, 4)
+    _say(f"  max in flight {max_flight}")
+    _check_same(reqs, alone, served)
+    assert max_flight >= 2          # requests overlapped on the device
+
+
+def test_small_budget_admits_as_memory_frees():
+    import paper_2504_09820_amd as fp
+
+    reqs = _requests(10, 11)
+    sizes = []
+    for r in reqs:
+        B, Nbs, K = r["H"].shape
+        el = r["H"].itemsize
+        sizes.append(B * (Nbs * K + Nbs * 14 + K * 14) * el + B * (8 + K * 14 + 4) + 6 * 256)
+    budget = int(2.2 * max(sizes))
+    _say(f"case serving: 10 requests, budget {budget} bytes (about two of the largest)")
+    alone = [_alone(fp, r) for r in reqs]
+    served, max_flight, max_held = _serve(fp, reqs, budget, 8)
+    _say(f"  max in flight {max_flight}, max device bytes held {max_held}")
+    _check_same(reqs, alone, served)
+    assert max_held <= budget

@@ -10,7 +10,7 @@ Signal model (paper, Sec. II): y = H x + n, with the Kronecker channel
 H = sqrt(R_r) Omega sqrt(R_t) (eq. channel_model), Omega i.i.d. CN(0, 1/M),
 and exponential correlation r_ij = zeta^(j-i) for i <= j, r_ji = conj(r_ij).
 
-Readings of points the paper leaves open (listed in the design doc as well):
+Readings of points the paper leaves open:
   * sqrt(R) is the symmetric PSD principal square root (eigen-decomposition
     with eigenvalues clipped at zero); the proof of Theorem 3 uses V^T = V.
   * The transmit correlation R_t spans all K streams (eqs. 3-4).
