@@ -104,6 +104,21 @@ fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out);
 /* Waits for the context's own streams, then frees everything it owns. */
 void fpcg_destroy(fpcg_ctx* ctx);
 
+/* Launch form of fpcg_detect for channels one wave solves (padded K <= 32)
+ * without refinement; larger K and refinement always use the fused form.
+ *   FPCG_LAUNCH_AUTO       (default) the library's choice: the fused form,
+ *                          which measured faster on every K <= 32 workload;
+ *   FPCG_LAUNCH_FUSED      one workgroup per channel doing every step;
+ *   FPCG_LAUNCH_PIPELINED  persistent two-wave workgroups, one wave forming
+ *                          the Gram and matched filter of the next channel
+ *                          while the other solves the current one from the
+ *                          other half of a double buffer in LDS.
+ * Both forms run the same per-channel arithmetic in the same order, so their
+ * results are bitwise identical; only the schedule of work differs.
+ * FPCG_E_INVAL for a NULL context or an unknown form. */
+enum { FPCG_LAUNCH_AUTO = 0, FPCG_LAUNCH_FUSED = 1, FPCG_LAUNCH_PIPELINED = 2 };
+fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form);
+
 /* Static description of a status code. */
 const char* fpcg_strerror(int32_t status);
 

@@ -79,6 +79,8 @@ def lib():
     L.fpcg_create.restype = st
     L.fpcg_destroy.argtypes = [vp]
     L.fpcg_destroy.restype = None
+    L.fpcg_set_launch_form.argtypes = [vp, i32]
+    L.fpcg_set_launch_form.restype = st
     L.fpcg_strerror.argtypes = [i32]
     L.fpcg_strerror.restype = ctypes.c_char_p
     L.fpcg_last_error.argtypes = []
@@ -138,6 +140,12 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def set_launch_form(self, form: str = "auto"):
+        """"auto" (the library's choice), "fused" (one workgroup per channel) or
+        "pipelined" (two-wave pipelined form where built); results are bitwise
+        the same."""
+        _check(lib().fpcg_set_launch_form(self._h, {"auto": 0, "fused": 1, "pipelined": 2}[form]))
 
     def close(self):
         if self._h:

@@ -105,16 +105,45 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr size_t sz_X = 2 * W * SH * NT;
     static constexpr size_t sz_X64 = 2 * 8 * (size_t)SH * NT;           // FP64 iterate [2][SH][NT]
     static_assert(sz_X <= 2 * W * KP * LDA, "x fits the Gram's slot");
+    static constexpr size_t sz_B = 2 * W * KP * 16;
+    static constexpr bool B_FITS = sz_X + sz_B <= 2 * W * KP * LDA;   // x and B in the Gram's slot
     // Once A sits in registers and no FP64 refresh reads the stored Gram, the
     // Gram's LDS is dead after the operand is packed and x moves into it.
     __host__ __device__ static constexpr bool x_in_gram(int refresh_every) { return AREG && refresh_every == 0; }
-    __host__ __device__ static constexpr size_t lds(bool split, bool refine, int refresh_every) {
+    // Compact layout (one workgroup per channel, no refinement, x in the Gram's
+    // slot): B is carried in registers through the block-Jacobi setup and then
+    // stored next to x, so the layout is [A (then x, B) | M | F | S].
+    __host__ __device__ static constexpr bool compact(bool refine, int refresh_every) {
+        return B_FITS && !refine && x_in_gram(refresh_every);
+    }
+    // bytes of the general layout [A | B | M | F | S | X | X64]
+    __host__ __device__ static constexpr size_t lds_general(bool split, bool refine, int refresh_every) {
         return off_X(split) + (x_in_gram(refresh_every) ? 0 : sz_X) + (refine ? sz_X64 : 0);
+    }
+    // bytes of a one-workgroup-per-channel launch
+    __host__ __device__ static constexpr size_t lds(bool split, bool refine, int refresh_every) {
+        return compact(refine, refresh_every) ? off_X(split) - sz_B : lds_general(split, refine, refresh_every);
     }
 };
 
-template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1 : Cfg<KP, NW, FMT, LB>::MIN_WAVES))) void fused_kernel(const FusedParams P) {
+// How a call of detect_channel is used: the whole path by every wave of the
+// workgroup (FULL), or one role of the pipelined kernel (one wave each).
+enum : int { MODE_FULL = 0, MODE_GRAM = 1, MODE_SOLVE = 2 };
+
+// LDS of one wave ordered against itself (the roles of the pipelined kernel
+// synchronise only within their own wave)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One channel (and one block of up to 16 received vectors): the Gram and
+// matched filter into the buffer `sbuf` ([Ar | Ai | Br | Bi]), then the
+// solve from it using the private regions at `spriv` + the Cfg offsets.
+template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT, int MODE>
+__device__ __forceinline__ void detect_channel(const FusedParams& P, const int64_t ch, const int cblk,
+                                               unsigned char* sbuf, unsigned char* spriv, uint32_t* sgflag,
+                                               const int tid) {
     using C = Cfg<KP, NW, FMT, LB>;
     using O = typename C::O;
     using OG = typename C::OG;
@@ -125,22 +154,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
     constexpr int SH = C::SH, NF = C::NF, NKB = C::NKB, F = C::F, KPL = C::KPL;
     constexpr int KPLG = C::KPLG, KBG = C::KBG, LDA = C::LDA, PPW = C::PPW, MFPW = C::MFPW;
     constexpr int NT = C::NT;
+    static_assert(MODE == MODE_FULL || NW == 1, "pipelined roles are one wave each");
 
-    extern __shared__ __align__(16) unsigned char smem[];
-    Wt* sAr = reinterpret_cast<Wt*>(smem + C::off_Ar);
-    Wt* sAi = reinterpret_cast<Wt*>(smem + C::off_Ai);
-    Wt* sBr = reinterpret_cast<Wt*>(smem + C::off_Br);
-    Wt* sBi = reinterpret_cast<Wt*>(smem + C::off_Bi);
-    Wt* sMr = reinterpret_cast<Wt*>(smem + C::off_M);
-    Wt* sMi = sMr + KP * (LB ? LB : 1);
+    auto bsync = [&]() {
+        if constexpr (MODE == MODE_FULL) __syncthreads();
+        else wave_sync();
+    };
     const bool x_in_gram = C::x_in_gram(P.refresh_every);
+    const bool compact = MODE == MODE_FULL && C::compact(REF, P.refresh_every);
+    const size_t shift = compact ? C::sz_B : 0;       // the compact layout has no B slot after A
+    Wt* sAr = reinterpret_cast<Wt*>(sbuf + C::off_Ar);
+    Wt* sAi = reinterpret_cast<Wt*>(sbuf + C::off_Ai);
+    Wt* sBr = reinterpret_cast<Wt*>(compact ? sbuf + C::off_Ar + C::sz_X : sbuf + C::off_Br);
+    Wt* sBi = sBr + KP * 16;
+    Wt* sMr = reinterpret_cast<Wt*>(spriv + C::off_M - shift);
+    Wt* sMi = sMr + KP * (LB ? LB : 1);
     constexpr size_t off_X = C::off_X(LB > 0 && SPLIT);
-    Wt* sXr = reinterpret_cast<Wt*>(smem + (x_in_gram ? C::off_Ar : off_X));   // x, [SH][NT]
+    Wt* sXr = reinterpret_cast<Wt*>(x_in_gram ? sbuf + C::off_Ar : spriv + off_X);   // x, [SH][NT]
     Wt* sXi = sXr + SH * NT;
-    frag* sF = reinterpret_cast<frag*>(smem + C::off_F);
-    double* sX64r = reinterpret_cast<double*>(smem + off_X + (x_in_gram ? 0 : C::sz_X));   // refinement only
+    frag* sF = reinterpret_cast<frag*>(spriv + C::off_F - shift);
+    double* sX64r = reinterpret_cast<double*>(spriv + off_X + (x_in_gram ? 0 : C::sz_X));   // refinement only
     double* sX64i = sX64r + SH * NT;
-    unsigned char* scr = smem + C::off_S;
+    unsigned char* scr = spriv + C::off_S - shift;
     double* sXP = reinterpret_cast<double*>(scr);                       // [NW][64][2*SH]
     double* sRed = reinterpret_cast<double*>(scr + C::sz_xp);          // [2][NW][16][4]
     double* sRef = reinterpret_cast<double*>(scr + C::sz_xp + C::sz_red);   // [NW][RC][16][2]
@@ -148,10 +183,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
     __shared__ float sMaxW[NW];
     __shared__ float sMaxC[NW][16];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, n = lane & 15;
-    const int64_t ch = blockIdx.x;
-    const int col = blockIdx.y * 16 + n;
+    const int col = cblk * 16 + n;
     const bool colv = col < P.R;
     const int K = P.K, Nbs = P.Nbs, R = P.R;
     const int64_t hoff = ch * (int64_t)Nbs * K;
@@ -162,7 +196,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
     auto hofs = [&](int a, int k) -> uint32_t { return (a < Nbs && k < K) ? ((uint32_t)a * K + k) * ES : OOB; };
     auto yofs = [&](int a) -> uint32_t { return (a < Nbs && colv) ? ((uint32_t)a * R + col) * ES : OOB; };
     const double s2 = P.sigma2[ch];
-    if (tid == 0) sFlag = 0u;
+    if constexpr (MODE == MODE_FULL) {
+        if (tid == 0) sFlag = 0u;
+    }
     uint32_t myflag = 0u;
 
     // block-wide max over one float per thread (fixed order, result in all threads)
@@ -192,6 +228,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
         return v;
     };
 
+    // B carried in registers (compact layout), stored once A is packed
+    Wt bcr[C::MFPW][4], bci[C::MFPW][4];
+    if constexpr (MODE != MODE_SOLVE) {
     // ------------------------------------------------------------ fp8 scales
     int eH = 0, eY = 0;
     if constexpr (FMT == F8) {
@@ -324,14 +363,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
                     Wt br = (Wt)gBr[s][jj], bi = (Wt)gBi[s][jj];
                     if constexpr (FMT == F8) { br = br * invH * invY; bi = bi * invH * invY; }
                     bad |= !__builtin_isfinite(br) || !__builtin_isfinite(bi);
-                    sBr[row * 16 + n] = br;
-                    sBi[row * 16 + n] = bi;
+                    bcr[s][jj] = br;
+                    bci[s][jj] = bi;
+                    if (!compact) {
+                        sBr[row * 16 + n] = br;
+                        sBi[row * 16 + n] = bi;
+                    }
                 }
             }
         }
         if (bad) myflag |= FLAG_NONFINITE;
     }
-    __syncthreads();
+    }
+    if constexpr (MODE == MODE_GRAM) {
+        // hand the buffer's flag to the solving wave
+        const bool nf = __ballot((myflag & FLAG_NONFINITE) != 0) != 0;
+        if (tid == 0) *sgflag = nf ? FLAG_NONFINITE : 0u;
+        wave_sync();
+        return;
+    } else {
+        if constexpr (MODE == MODE_SOLVE) myflag = *sgflag;
+        bsync();
+    }
 
 
     constexpr bool split = (LB > 0) && SPLIT;          // symmetric form of Alg. 3
@@ -412,7 +465,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
             }
             if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
         }
-        __syncthreads();
+        bsync();
         if constexpr (!split) {
             // M = T^H T: row i
             // with column i of T in this lane's registers; T is lower triangular
@@ -431,7 +484,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
                     sMi[(cb + i) * LB + j] = mi;
                 }
             }
-            __syncthreads();
+            bsync();
         } else {
             // A <- T A T^H in place, upper triangle only (the lower one is read as
             // its conjugate, the diagonal as real: the result is Hermitian by
@@ -482,7 +535,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
                     for (int c = 0; c < LB; ++c) { sAr[m * LDA + b * LB + c] = w_r[c]; sAi[m * LDA + b * LB + c] = w_i[c]; }
                 }
             }
-            __syncthreads();
+            bsync();
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int nn = q + it * RPL;
@@ -508,7 +561,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
                     for (int r = 0; r < LB; ++r) { sAr[(b * LB + r) * LDA + nn] = v_r[r]; sAi[(b * LB + r) * LDA + nn] = v_i[r]; }
                 }
             }
-            __syncthreads();
+            bsync();
         }
     }
 
@@ -582,6 +635,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
     }
     if constexpr (NW > 1) {
         if (x_in_gram) __syncthreads();               // every wave has packed before x overwrites the Gram
+    }
+    if (compact) {
+        // B into the Gram's slot, next to x (the packing above has read A)
+        bsync();
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            if (NW == 1 || f % NW == wave) {
+                const int s = f / NW;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int row = 16 * f + OG::crow(g, jj);
+                    sBr[row * 16 + n] = bcr[s][jj];
+                    sBi[row * 16 + n] = bci[s][jj];
+                }
+            }
+        }
+        bsync();
     }
     auto A_op = [&](int phi, int ws, int kb, int ri) -> frag {
         if constexpr (C::AREG) {
@@ -846,7 +916,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
                 sBr[c * 16 + n] = (Wt)resr[e];
                 sBi[c * 16 + n] = (Wt)resi[e];
             }
-            __syncthreads();
+            bsync();
         }
 
         // ------------------------------------------------ 3. (P)CG
@@ -1080,11 +1150,101 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REF ? 1
             }
         }
     }
-    if (myflag) atomicOr(&sFlag, myflag);
+    const bool one_block = P.R <= 16;                  // the only workgroup / item of this channel
+    if constexpr (MODE == MODE_FULL) {
+        if (myflag) atomicOr(&sFlag, myflag);
+        __syncthreads();
+        if (tid == 0 && P.flags) {
+            if (one_block) P.flags[ch] = sFlag;
+            else if (sFlag) atomicOr(&P.flags[ch], sFlag);     // flags were cleared before the launch
+        }
+    } else {
+        uint32_t f = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (__ballot((myflag >> b) & 1u) != 0) f |= 1u << b;
+        if (tid == 0 && P.flags) {
+            if (one_block) P.flags[ch] = f;
+            else if (f) atomicOr(&P.flags[ch], f);
+        }
+    }
+}
+
+// Register budget of a one-workgroup-per-channel build, in waves per SIMD:
+// four where the allocation fits 128 registers without spilling (measured:
+// K <= 32, fp16 / bf16 operands, symmetric L = 4, complex64 I/O), three for
+// the other K <= 32 reduced-precision and FP32 builds, no constraint for
+// FP64, K = 64 and refinement builds.
+template <int KP, int FMT, int LB, bool SPLIT, bool REF, typename IOT> constexpr int fused_waves() {
+    if (REF) return 1;
+    if (KP == 32 && (FMT == F16 || FMT == BF16) && LB == 4 && SPLIT && sizeof(IOT) == 4) return 4;
+    return Cfg<KP, 1, FMT, LB>::MIN_WAVES;
+}
+
+template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(fused_waves<KP, FMT, LB, SPLIT, REF, IOT>())))
+void fused_kernel(const FusedParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    detect_channel<KP, NW, FMT, LB, SPLIT, REF, IOT, MODE_FULL>(P, blockIdx.x, blockIdx.y, smem, smem, nullptr,
+                                                                 threadIdx.x);
+}
+
+// Pipelined form for one-wave channels: a persistent workgroup of two waves
+// walks its items (channel, block of received vectors) in steps; in step k
+// wave 0 forms the Gram and matched filter of item k+1 into one LDS buffer
+// while wave 1 solves item k from the other, so the HBM stream of the Gram
+// overlaps the on-chip solve.  LDS: [buffer 0 | buffer 1 | solver regions].
+template <int KP, int FMT, int LB> struct PipeCfg {
+    using C = Cfg<KP, 1, FMT, LB>;
+    static constexpr size_t BUF = C::off_M;           // [Ar | Ai | Br | Bi]
+    __host__ __device__ static constexpr size_t lds(bool split, int refresh_every) {
+        return BUF + C::lds_general(split, false, refresh_every);
+    }
+};
+
+template <int KP, int FMT, int LB, bool SPLIT, typename IOT>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(Cfg<KP, 1, FMT, LB>::MIN_WAVES)))
+void pipe_kernel(const FusedParams P) {
+    constexpr size_t BUF = PipeCfg<KP, FMT, LB>::BUF;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t gflag[2];
+    // the role is uniform per wave: a scalar branch, so the roles' code never shares registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane0 = threadIdx.x & 63;
+    const int ncb = (P.R + 15) / 16;
+    const int64_t items = P.B * ncb, G = gridDim.x;
+    int64_t it = blockIdx.x;
+    // the buffer of each role is a compile-time offset in both halves of a
+    // step pair, so LDS addresses fold into the instructions' offsets
+    auto step = [&](auto cur_c) {
+        constexpr int cur = decltype(cur_c)::value, nxt = cur ^ 1;
+        // an opaque copy of the lane index per step keeps the compiler from
+        // hoisting every lane-dependent address of both roles out of the loop
+        // (they would stay live across the whole loop and spill)
+        int lane = lane0;
+        asm volatile("" : "+v"(lane));
+        if (wave == 0) {
+            const int64_t nit = it + G;
+            if (nit < items)
+                detect_channel<KP, 1, FMT, LB, SPLIT, false, IOT, MODE_GRAM>(P, nit / ncb, (int)(nit % ncb),
+                                                                              smem + nxt * BUF, smem + BUF,
+                                                                              &gflag[nxt], lane);
+        } else {
+            detect_channel<KP, 1, FMT, LB, SPLIT, false, IOT, MODE_SOLVE>(P, it / ncb, (int)(it % ncb),
+                                                                           smem + cur * BUF, smem + BUF,
+                                                                           &gflag[cur], lane);
+        }
+        __syncthreads();
+        it += G;
+    };
+    if (wave == 0 && it < items)
+        detect_channel<KP, 1, FMT, LB, SPLIT, false, IOT, MODE_GRAM>(P, it / ncb, (int)(it % ncb), smem, smem + BUF,
+                                                                      &gflag[0], lane0);
     __syncthreads();
-    if (tid == 0 && P.flags) {
-        if (gridDim.y == 1) P.flags[ch] = sFlag;           // the only workgroup of this channel
-        else if (sFlag) atomicOr(&P.flags[ch], sFlag);     // flags were cleared before the launch
+    // the loop bound depends on blockIdx only, so both waves meet every barrier
+    while (it < items) {
+        step(std::integral_constant<int, 0>{});
+        if (it >= items) break;
+        step(std::integral_constant<int, 1>{});
     }
 }
 

@@ -8,8 +8,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "fpcg.h"
@@ -137,7 +139,34 @@ static inline unsigned grid_for(int64_t n, int threads) {
     return (unsigned)b;
 }
 
-fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+static int cu_count(int device) {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(device);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1) n = 1;
+    cache[device] = n;
+    return n;
+}
+
+// resident two-wave workgroups per CU for a pipelined build and LDS size
+static int pipe_occupancy(int device, const void* fn, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_tuple(device, fn, lds);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 128, lds) != hipSuccess) nb = 0;
+    cache[key] = nb;
+    return nb;
+}
+
+fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K, int32_t R,
                           const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,
                           int32_t iters, void* xhat, uint8_t* labels, uint32_t* flags) {
     const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
@@ -152,7 +181,6 @@ fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int6
                         (void)hipFuncSetAttribute(t.fn[sp][r], hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   (int)t.lds(sp != 0, r != 0, 1));
     });
-    (void)device;
     if (flags && R > 16) {   // several workgroups per channel OR their flags together
         hipLaunchKernelGGL(zero_u32, dim3(grid_for(B, 256)), dim3(256), 0, stream, flags, B);
     }
@@ -166,9 +194,23 @@ fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int6
     p.bits = 0;
     while ((1 << p.bits) < p.m) ++p.bits;
     p.nu = std::sqrt(2.0 * (qam - 1) / 3.0);
-    dim3 grid((unsigned)B, (unsigned)((R + 15) / 16));
     const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
     const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
+    const int ncb = (R + 15) / 16;
+    if (!ref && e->pipe_fn[sp] && ctx->launch_form == FPCG_LAUNCH_PIPELINED) {
+        // pipelined form: persistent two-wave workgroups, as many as fit at once
+        const size_t lds = e->pipe_lds(sp != 0, p.refresh_every);
+        const int per_cu = pipe_occupancy(ctx->device, e->pipe_fn[sp], lds);
+        if (per_cu > 0) {
+            const int64_t items = B * ncb;
+            const int64_t g = std::min<int64_t>(items, (int64_t)per_cu * cu_count(ctx->device));
+            e->pipe_launch[sp](p, dim3((unsigned)g), lds, stream);
+            hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return fail(FPCG_E_DEVICE, "pipelined kernel launch: %s", hipGetErrorString(err));
+            return FPCG_OK;
+        }
+    }
+    dim3 grid((unsigned)B, (unsigned)ncb);
     const size_t lds = e->lds(sp != 0, ref != 0, p.refresh_every);   // within 160 KiB (check_args)
     e->launch[sp][ref](p, grid, lds, stream);
     hipError_t err = hipGetLastError();
@@ -230,6 +272,14 @@ fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out) {
 
 void fpcg_destroy(fpcg_ctx* ctx) { delete ctx; }
 
+fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form) {
+    clear_error();
+    if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    if (form < FPCG_LAUNCH_AUTO || form > FPCG_LAUNCH_PIPELINED) return fail(FPCG_E_INVAL, "launch form %d out of range", form);
+    ctx->launch_form = form;
+    return FPCG_OK;
+}
+
 fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam_order, int32_t iters,
                        int32_t block_L, const fpcg_schedule* sched) {
     clear_error();
@@ -247,7 +297,7 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int
     if (B > 0 && (!H || !Y || !sigma2 || !xhat || !labels))
         return fail(FPCG_E_INVAL, "H, Y, sigma2, xhat and labels must be non-NULL");
     ScopedDevice sd(ctx->device);
-    return launch_detect(ctx->device, (hipStream_t)stream, plan, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters,
+    return launch_detect(ctx, (hipStream_t)stream, plan, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters,
                          xhat, labels, flags);
 }
 

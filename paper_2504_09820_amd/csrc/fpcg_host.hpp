@@ -11,6 +11,7 @@
 struct fpcg_ctx {
     int device = 0;
     size_t budget = 0;
+    int launch_form = FPCG_LAUNCH_AUTO;
 };
 
 namespace fpcg {
@@ -26,7 +27,7 @@ void clear_error();
 fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam, int32_t iters, int32_t L,
                        const fpcg_schedule* s, Plan* plan);
 
-fpcg_status launch_detect(int device, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K,
+fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K,
                           int32_t R, const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,
                           int32_t iters, void* xhat, uint8_t* labels, uint32_t* flags);
 

@@ -15,6 +15,10 @@ struct KernelEntry {
     // builds of the kernel: [symmetric block-Jacobi form][FP64 refinement]
     const void* fn[2][2];
     void (*launch[2][2])(const FusedParams&, dim3, size_t, hipStream_t);
+    // the pipelined two-wave form ([symmetric form]; no refinement), when built
+    const void* pipe_fn[2] = {nullptr, nullptr};
+    void (*pipe_launch[2])(const FusedParams&, dim3, size_t, hipStream_t) = {nullptr, nullptr};
+    size_t (*pipe_lds)(bool split, int refresh_every) = nullptr;
 };
 
 void register_f64(std::vector<KernelEntry>& v);
@@ -53,6 +57,22 @@ void add_entry(std::vector<KernelEntry>& v) {
     } else {
         e.fn[1][0] = e.fn[0][0]; e.fn[1][1] = e.fn[0][1];
         e.launch[1][0] = e.launch[0][0]; e.launch[1][1] = e.launch[0][1];
+    }
+    if constexpr (NW == 1 && KP <= 32) {
+        e.pipe_lds = [](bool sp, int f) -> size_t { return PipeCfg<KP, FMT, LB>::lds(LB > 0 && sp, f); };
+        e.pipe_fn[0] = reinterpret_cast<const void*>(&pipe_kernel<KP, FMT, LB, false, IOT>);
+        e.pipe_launch[0] = [](const FusedParams& p, dim3 grid, size_t lds, hipStream_t s) {
+            hipLaunchKernelGGL((pipe_kernel<KP, FMT, LB, false, IOT>), grid, dim3(128), lds, s, p);
+        };
+        if constexpr (LB > 0) {
+            e.pipe_fn[1] = reinterpret_cast<const void*>(&pipe_kernel<KP, FMT, LB, true, IOT>);
+            e.pipe_launch[1] = [](const FusedParams& p, dim3 grid, size_t lds, hipStream_t s) {
+                hipLaunchKernelGGL((pipe_kernel<KP, FMT, LB, true, IOT>), grid, dim3(128), lds, s, p);
+            };
+        } else {
+            e.pipe_fn[1] = e.pipe_fn[0];
+            e.pipe_launch[1] = e.pipe_launch[0];
+        }
     }
     v.push_back(e);
 }

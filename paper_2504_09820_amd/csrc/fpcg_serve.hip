@@ -148,7 +148,7 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
         fpcg_status st = FPCG_OK;
         if (e != hipSuccess) st = fail(FPCG_E_DEVICE, "H2D copy: %s", hipGetErrorString(e));
         if (st == FPCG_OK)
-            st = launch_detect(s->ctx->device, sl.stream, rq->plan, r.B, r.Nbs, r.K, r.R, db + L.h, db + L.y, r.io_c64,
+            st = launch_detect(s->ctx, sl.stream, rq->plan, r.B, r.Nbs, r.K, r.R, db + L.h, db + L.y, r.io_c64,
                                reinterpret_cast<const double*>(db + L.s2), r.qam_order, r.iters, db + L.x,
                                reinterpret_cast<uint8_t*>(db + L.lab), reinterpret_cast<uint32_t*>(db + L.fl));
         if (st == FPCG_OK) {

@@ -115,3 +115,8 @@ def test_no_cpu_fallback_without_device(fp):
         pytest.skip("a GPU is present")
     with pytest.raises(fp.FpcgError):
         fp.Context(0)
+
+
+def test_launch_form_rejects_unknown(fp):
+    L = fp.lib()
+    assert L.fpcg_set_launch_form(None, 0) == -1

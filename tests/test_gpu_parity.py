@@ -322,3 +322,45 @@ def test_full_size_sampled(cfg, sched, L, iters, refresh, variant):
     _say(f"  full-batch BER {ber:.4f} (oracle on the sample {ber_o:.4f})")
     # the full batch's BER is that of the oracle's sample up to sampling error
     assert abs(ber - ber_o) <= 5 * np.sqrt(ber_o * (1 - ber_o) / nbits) + 1e-3
+
+
+# --------------------------------------------------------------- launch forms
+@pytest.mark.parametrize("sched,L,variant,refresh,B,R", [
+    ("fp16", 4, 2, 0, 3000, 14), ("bf16", 8, 0, 0, 2500, 14), ("fp32", 0, 0, 3, 2000, 14), ("fp8", 8, 2, 0, 2000, 14),
+    ("fp64", 0, 0, 0, 1800, 14), ("fp16", 4, 2, 4, 1000, 37),
+])
+def test_pipelined_and_fused_forms_agree_bitwise(sched, L, variant, refresh, B, R):
+    """The pipelined two-wave form (several channels per persistent workgroup,
+    double-buffered Gram) and the one-workgroup-per-channel form run the same
+    per-channel arithmetic: bitwise identical outputs.  B is large enough that
+    every persistent workgroup walks several channels; R = 37 also splits each
+    channel into three blocks of received vectors."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    _say(f"case launch forms {sched} L={L} v{variant} refresh={refresh} B={B} R={R}")
+    wl = _wl(B, 128, 32, R, 64, 20.0, 0.5, 31)
+    io = np.complex128 if sched == "fp64" else np.complex64
+    dev = torch.device("cuda:0")
+    Ht = torch.from_numpy(wl.H.astype(io)).to(dev)
+    Yt = torch.from_numpy(wl.Y.astype(io)).to(dev)
+    st = torch.from_numpy(wl.sigma2).to(dev)
+    outs = []
+    for form in ("pipelined", "fused"):
+        ctx = fp.Context(0)
+        ctx.set_launch_form(form)
+        x, lab, fl = fp.detect(Ht, Yt, st, 64, 12, L, sched, refresh_every=refresh, variant=variant, ctx=ctx)
+        torch.cuda.synchronize()
+        outs.append((x.cpu().numpy(), lab.cpu().numpy(), fl.cpu().numpy()))
+        ctx.close()
+    (xa, la, fa), (xb, lb, fb) = outs
+    assert np.array_equal(xa.view(np.uint8), xb.view(np.uint8))
+    assert np.array_equal(la, lb)
+    assert np.array_equal(fa, fb)
+    # and the pipelined result is the oracle's on sampled channels
+    idx = np.array([0, 1, B // 2, B - 2, B - 1])
+    sub = W.Workload(H=wl.H[idx], Y=wl.Y[idx], labels=wl.labels[idx], X=wl.X[idx], sigma2=wl.sigma2[idx],
+                     q=64, snr_db=wl.snr_db[idx])
+    spread, ref = oracle_spread(sub, 64, 12, L, sched, io, refresh=refresh, variant=variant)
+    _spread_parity(xa[idx].astype(np.complex128), ref, spread, sched, f"launch forms {sched}", io)
