@@ -14,10 +14,13 @@ launch.  The method timed is FP-BJ-CG (Alg. 3 in its symmetric form): the
 operand format is the one the precision heuristic (eq. heuristic_bj) selects
 for the expected condition number of the preconditioned system, the Jacobi
 block size is the faster of L = 4 and L = 8 at BER parity, and the iteration
-counts come from a BER-parity search on a 4096-channel slice of the batch:
-    I64 = smallest I whose FP64 CG bit-error rate is within 2 % of the
-          converged (3K-iteration) FP64 solve,
+counts come from a BER-parity search at the 1e-3 operating point: on a
+4096-channel slice of the batch (its channels, symbols and noise realisation
+kept, the noise rescaled) the SNR where the converged (3K-iteration) FP64 solve
+crosses BER 1e-3 is found, and there
+    I64 = smallest I whose FP64 CG bit-error rate is within 2 % of the converged one,
     Imp = smallest I whose FP-BJ-CG bit-error rate is within 2 % of FP64 CG's at I64.
+The SNR gap at BER 1e-3 between FP-BJ-CG (Imp) and FP64 CG (I64) is reported.
 FP64 CG (Alg. 2, FP64 matrix cores) is timed at I64 on the same batch and GPU.
 
 Prints one JSON line on stdout; everything else goes to stderr.
@@ -104,7 +107,7 @@ def write_traffic(args, fetch_csv, write_csv):
         res[counter] = {"kib_per_launch_raw": float(np.mean(fused)), "copy_kib_raw": float(np.mean(copies)),
                         "scale": scale, "bytes_per_launch": float(np.mean(fused)) * 1024 * scale}
     L = int(args.L) if args.L != "auto" else 4
-    it = args.iters or 12
+    it = args.iters or 11
     rec = {"config": args.config, "schedule": args.schedule, "L": L, "variant": args.variant, "iters": it,
            "kernel_source_hash": kernel_source_hash(),
            "hbm_bytes_per_launch": round(res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]),
@@ -201,7 +204,7 @@ def main():
 
     if args.profile:
         cd = cands[0]
-        it = args.iters or 12
+        it = args.iters or 11
         wall, per = run(cd["sched"], it, cd["L"], variant, args.steps, args.warmup)
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # a plain copy of known size, to scale
         b = torch.empty_like(a)                                     # the HBM byte counters
@@ -213,39 +216,81 @@ def main():
                           "kernel_ms_mean": float(np.mean(per)), "kernel_source_hash": kernel_source_hash()}))
         return
 
-    # ------------------------------------------------------------ BER-parity iteration counts
+    # ------------------------------------------------------------ BER parity at the 1e-3 operating point
+    # A 4096-channel slice of the same draw; other SNRs reuse its channels,
+    # symbols and noise realisation (common random numbers): Y = H X + n s.
     nb = min(B, 4096)
-    Hs, Ys, ss, ts = H[:nb], Y[:nb], s2[:nb], tx[:nb]
+    Hs, ts = H[:nb], tx[:nb]
+    HX = torch.matmul(Hs.to(torch.complex128), torch.from_numpy(wl.X[:nb]).to(dev))
+    N0 = Y[:nb].to(torch.complex128) - HX
+    sig0 = float(wl.sigma2[0])
 
-    def ber_at(s, it, LL, v=0):
-        _, lab, _ = fp.detect(Hs, Ys, ss, q, it, LL, s, variant=v, ctx=ctx)
+    def inputs_at(snr_db):
+        s2_ = W.sigma2_from_snr_db(snr_db, Nbs, c["normalization"])
+        Ys_ = (HX + N0 * math.sqrt(s2_ / sig0)).to(torch.complex64)
+        return Ys_, torch.full((nb,), s2_, dtype=torch.float64, device=dev)
+
+    def ber_at(s, it, LL, v, snr_db):
+        Ys_, ss_ = inputs_at(snr_db)
+        _, lab, _ = fp.detect(Hs, Ys_, ss_, q, it, LL, s, variant=v, ctx=ctx)
         return ber_of(lab, ts, q)
 
-    berconv = ber_at("fp64", 3 * K, 0)
+    def crossing(points, target=1e-3):
+        """SNR where log10(BER) crosses target, by linear interpolation in dB."""
+        pts = sorted(points)
+        for (s0, b0), (s1, b1) in zip(pts, pts[1:]):
+            if b0 > target >= b1 and b1 > 0:
+                t = (math.log10(b0) - math.log10(target)) / (math.log10(b0) - math.log10(b1))
+                return s0 + t * (s1 - s0)
+        return None
+
+    conv = {}
+    snr = float(c["snr_db"])
+    while snr <= 45.0:
+        conv[snr] = ber_at("fp64", 3 * K, 0, 0, snr)
+        if conv[snr] <= 1e-3:
+            break
+        snr += 1.0
+    snr_op = crossing(list(conv.items())) or snr
+    berconv = ber_at("fp64", 3 * K, 0, 0, snr_op)
     I64 = args.iters64
     if not I64:
         I64 = 3 * K
         for it in range(2, 3 * K + 1):
-            if ber_at("fp64", it, 0) <= berconv * 1.02:
+            if ber_at("fp64", it, 0, 0, snr_op) <= berconv * 1.02:
                 I64 = it
                 break
-    ber64 = ber_at("fp64", I64, 0)
-    log(f"BER: converged FP64 {berconv:.5f}; FP64 CG I64={I64} {ber64:.5f}")
+    ber64 = ber_at("fp64", I64, 0, 0, snr_op)
+    log(f"BER 1e-3 operating point: converged FP64 crosses 1e-3 at {snr_op:.2f} dB (BER {berconv:.2e}); "
+        f"FP64 CG I64={I64} {ber64:.2e}")
     for cd in cands:
         imp = args.iters
         if not imp:
             imp = 3 * K
             for it in range(1, 3 * K + 1):
-                if ber_at(cd["sched"], it, cd["L"], variant) <= ber64 * 1.02:
+                if ber_at(cd["sched"], it, cd["L"], variant, snr_op) <= ber64 * 1.02:
                     imp = it
                     break
         cd["iters"] = imp
-        cd["ber"] = ber_at(cd["sched"], imp, cd["L"], variant)
+        cd["ber"] = ber_at(cd["sched"], imp, cd["L"], variant, snr_op)
         _, per = run(cd["sched"], imp, cd["L"], variant, 10, 3)
         cd["p50_ms"] = float(np.median(per))
-        log(f"  {cd['sched']} L={cd['L']} v{variant}: Imp={imp} BER {cd['ber']:.5f}, kernel p50 {cd['p50_ms']:.4f} ms")
+        log(f"  {cd['sched']} L={cd['L']} v{variant}: Imp={imp} BER {cd['ber']:.2e}, kernel p50 {cd['p50_ms']:.4f} ms")
     best = min(cands, key=lambda d: d["p50_ms"])
     sched, L, Imp = best["sched"], best["L"], best["iters"]
+
+    # BER-vs-SNR gap at 1e-3 between the timed schedule and FP64 CG (and the converged solve)
+    grid = [round(snr_op + d, 2) for d in (-2.0, -1.0, 0.0, 1.0, 2.0)]
+    curves = {"converged": [], "fp64_cg": [], "mixed": []}
+    for sn in grid:
+        curves["converged"].append((sn, ber_at("fp64", 3 * K, 0, 0, sn)))
+        curves["fp64_cg"].append((sn, ber_at("fp64", I64, 0, 0, sn)))
+        curves["mixed"].append((sn, ber_at(sched, Imp, L, variant, sn)))
+    snr_at = {k: crossing(v) for k, v in curves.items()}
+    gap64 = None if None in (snr_at["mixed"], snr_at["fp64_cg"]) else snr_at["mixed"] - snr_at["fp64_cg"]
+    gapc = None if None in (snr_at["mixed"], snr_at["converged"]) else snr_at["mixed"] - snr_at["converged"]
+    log(f"SNR at BER 1e-3: converged {snr_at['converged']}, FP64 CG {snr_at['fp64_cg']}, {sched} L={L} "
+        f"{snr_at['mixed']}; gap vs FP64 CG {gap64} dB")
 
     # ------------------------------------------------------------ timed runs
     wall_mp, per_mp = run(sched, Imp, L, variant, args.steps, args.warmup)
@@ -271,7 +316,8 @@ def main():
         except (OSError, ValueError):
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel_ms_mean": round(kern_ms, 5), "algorithmic_bytes": nbytes}
 
     # ------------------------------------------------------------ CPU oracle baseline
     cpu = None
@@ -316,7 +362,11 @@ def main():
         "fp64_cg": {"value": round(value64, 1), "ms_per_step": round(wall_64 / steps64 * 1e3, 5),
                     "p50_ms": round(float(np.median(per_64)), 5)},
         "speedup_vs_fp64_cg": round(value / value64, 3),
-        "ber": {"converged_fp64": berconv, "fp64_cg": ber64, "fp_bj_cg": best["ber"]},
+        "ber": {"operating_snr_db": round(snr_op, 3), "bits": int(nb * K * R * math.log2(q)),
+                "converged_fp64": berconv, "fp64_cg": ber64, "fp_bj_cg": best["ber"],
+                "snr_db_at_1e-3": {k: (None if v is None else round(v, 3)) for k, v in snr_at.items()},
+                "gap_db_vs_fp64_cg": None if gap64 is None else round(gap64, 3),
+                "gap_db_vs_converged": None if gapc is None else round(gapc, 3)},
         "heuristic": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in cd.items()} for cd in cands],
         "roofline": roofline,
         "cpu_baseline": cpu,
