@@ -106,8 +106,8 @@ void fpcg_destroy(fpcg_ctx* ctx);
 
 /* Launch form of fpcg_detect for channels one wave solves (padded K <= 32)
  * without refinement; larger K and refinement always use the fused form.
- *   FPCG_LAUNCH_AUTO       (default) the library's choice: the fused form,
- *                          which measured faster on every K <= 32 workload;
+ *   FPCG_LAUNCH_AUTO       (default) the form fpcg_autotune chose for the
+ *                          launch's shape class, else the fused form;
  *   FPCG_LAUNCH_FUSED      one workgroup per channel doing every step;
  *   FPCG_LAUNCH_PIPELINED  persistent two-wave workgroups, one wave forming
  *                          the Gram and matched filter of the next channel
@@ -118,6 +118,17 @@ void fpcg_destroy(fpcg_ctx* ctx);
  * FPCG_E_INVAL for a NULL context or an unknown form. */
 enum { FPCG_LAUNCH_AUTO = 0, FPCG_LAUNCH_FUSED = 1, FPCG_LAUNCH_PIPELINED = 2 };
 fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form);
+
+/* Autotuner: times every launch form built for the shape class of these
+ * arguments (padded K, operand format, block size and form, refresh on/off,
+ * I/O type, one or several blocks of received vectors) on synthetic inputs
+ * of this size, `reps` interleaved launches each (1..1000), and records the
+ * fastest in the context for FPCG_LAUNCH_AUTO; *chosen_form (may be NULL)
+ * receives it.  Allocates and frees its own device buffers and synchronises
+ * `stream`; arguments are validated as by fpcg_detect (B >= 1). */
+fpcg_status fpcg_autotune(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                          int32_t io_c64, int32_t qam_order, int32_t iters, int32_t block_L,
+                          const fpcg_schedule* sched, int32_t reps, int32_t* chosen_form);
 
 /* Static description of a status code. */
 const char* fpcg_strerror(int32_t status);

@@ -81,6 +81,9 @@ def lib():
     L.fpcg_destroy.restype = None
     L.fpcg_set_launch_form.argtypes = [vp, i32]
     L.fpcg_set_launch_form.restype = st
+    L.fpcg_autotune.argtypes = [vp, vp, i64, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Schedule), i32,
+                                ctypes.POINTER(i32)]
+    L.fpcg_autotune.restype = st
     L.fpcg_strerror.argtypes = [i32]
     L.fpcg_strerror.restype = ctypes.c_char_p
     L.fpcg_last_error.argtypes = []
@@ -140,6 +143,19 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def autotune(self, B, Nbs, K, R, qam, iters, L=0, schedule_: "str | Schedule" = "fp64", refresh_every=0,
+                 refine_steps=0, variant=0, io="complex64", reps=5, stream=None):
+        """Time the launch forms built for this shape class and keep the fastest
+        for launches in the "auto" form; returns its name."""
+        import torch
+
+        sched = schedule(schedule_, refresh_every, refine_steps, variant) if isinstance(schedule_, str) else schedule_
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        out = ctypes.c_int32()
+        _check(lib().fpcg_autotune(self._h, ctypes.c_void_p(s.cuda_stream), B, Nbs, K, R, 1 if io == "complex64" else 0,
+                                   qam, iters, L, ctypes.byref(sched), reps, ctypes.byref(out)))
+        return {1: "fused", 2: "pipelined"}[out.value]
 
     def set_launch_form(self, form: str = "auto"):
         """"auto" (the library's choice), "fused" (one workgroup per channel) or

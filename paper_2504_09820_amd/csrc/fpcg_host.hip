@@ -166,9 +166,24 @@ static int pipe_occupancy(int device, const void* fn, size_t lds) {
     return nb;
 }
 
-fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K, int32_t R,
-                          const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,
-                          int32_t iters, void* xhat, uint8_t* labels, uint32_t* flags) {
+TuneKey tune_key(const Plan& plan, int32_t R, int32_t io_c64) {
+    return TuneKey(plan.KP, plan.FMT, plan.LB, (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0,
+                   plan.sched.refresh_every > 0 ? 1 : 0, io_c64 ? 1 : 0, R > 16 ? 1 : 0);
+}
+
+std::vector<int> launch_forms(const Plan& plan, int32_t R, int32_t io_c64) {
+    (void)R;
+    std::vector<int> f{FPCG_LAUNCH_FUSED};
+    const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
+    const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
+    if (e && e->pipe_fn[sp] && plan.sched.refine_steps == 0) f.push_back(FPCG_LAUNCH_PIPELINED);
+    return f;
+}
+
+fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int form, int64_t B,
+                               int32_t Nbs, int32_t K, int32_t R, const void* H, const void* Y, int32_t io_c64,
+                               const double* sigma2, int32_t qam, int32_t iters, void* xhat, uint8_t* labels,
+                               uint32_t* flags) {
     const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
     if (!e) return fail(FPCG_E_UNSUPPORTED, "variant missing");
     if (B == 0) return FPCG_OK;
@@ -197,7 +212,7 @@ fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& p
     const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
     const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
     const int ncb = (R + 15) / 16;
-    if (!ref && e->pipe_fn[sp] && ctx->launch_form == FPCG_LAUNCH_PIPELINED) {
+    if (!ref && e->pipe_fn[sp] && form == FPCG_LAUNCH_PIPELINED) {
         // pipelined form: persistent two-wave workgroups, as many as fit at once
         const size_t lds = e->pipe_lds(sp != 0, p.refresh_every);
         const int per_cu = pipe_occupancy(ctx->device, e->pipe_fn[sp], lds);
@@ -216,6 +231,18 @@ fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& p
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(FPCG_E_DEVICE, "fused kernel launch: %s", hipGetErrorString(err));
     return FPCG_OK;
+}
+
+fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs,
+                          int32_t K, int32_t R, const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                          int32_t qam, int32_t iters, void* xhat, uint8_t* labels, uint32_t* flags) {
+    int form = ctx->launch_form;
+    if (form == FPCG_LAUNCH_AUTO) {
+        auto it = ctx->tuned.find(tune_key(plan, R, io_c64));
+        form = it != ctx->tuned.end() ? it->second : FPCG_LAUNCH_FUSED;
+    }
+    return launch_detect_form(ctx, stream, plan, form, B, Nbs, K, R, H, Y, io_c64, sigma2, qam, iters, xhat, labels,
+                              flags);
 }
 
 // ------------------------------------------------------------------ slicer / rounding kernels

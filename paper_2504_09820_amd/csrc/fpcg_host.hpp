@@ -5,13 +5,21 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <tuple>
+#include <vector>
 
 #include "fpcg.h"
+
+// shape class of a launch: padded K, operand format, Jacobi block size,
+// symmetric form, refresh on, complex64 I/O, several blocks of received vectors
+using fpcg_tune_key = std::tuple<int, int, int, int, int, int, int>;
 
 struct fpcg_ctx {
     int device = 0;
     size_t budget = 0;
     int launch_form = FPCG_LAUNCH_AUTO;
+    std::map<fpcg_tune_key, int> tuned;   // launch form chosen by fpcg_autotune per shape class
 };
 
 namespace fpcg {
@@ -26,6 +34,16 @@ void clear_error();
 
 fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam, int32_t iters, int32_t L,
                        const fpcg_schedule* s, Plan* plan);
+
+using TuneKey = fpcg_tune_key;
+TuneKey tune_key(const Plan& plan, int32_t R, int32_t io_c64);
+// launch forms built for a plan (FPCG_LAUNCH_FUSED first)
+std::vector<int> launch_forms(const Plan& plan, int32_t R, int32_t io_c64);
+// one launch in the given form (FPCG_LAUNCH_FUSED or FPCG_LAUNCH_PIPELINED)
+fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int form, int64_t B,
+                               int32_t Nbs, int32_t K, int32_t R, const void* H, const void* Y, int32_t io_c64,
+                               const double* sigma2, int32_t qam, int32_t iters, void* xhat, uint8_t* labels,
+                               uint32_t* flags);
 
 fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K,
                           int32_t R, const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,

@@ -120,3 +120,13 @@ def test_no_cpu_fallback_without_device(fp):
 def test_launch_form_rejects_unknown(fp):
     L = fp.lib()
     assert L.fpcg_set_launch_form(None, 0) == -1
+
+
+def test_autotune_validates_before_touching_a_device(fp):
+    L = fp.lib()
+    s = fp.schedule("fp16")
+    import ctypes as ct
+
+    out = ct.c_int32(-7)
+    assert L.fpcg_autotune(None, None, 16, 128, 32, 14, 1, 64, 8, 4, ct.byref(s), 3, ct.byref(out)) == -1
+    assert out.value == -7

@@ -364,3 +364,77 @@ def test_pipelined_and_fused_forms_agree_bitwise(sched, L, variant, refresh, B, 
                      q=64, snr_db=wl.snr_db[idx])
     spread, ref = oracle_spread(sub, 64, 12, L, sched, io, refresh=refresh, variant=variant)
     _spread_parity(xa[idx].astype(np.complex128), ref, spread, sched, f"launch forms {sched}", io)
+
+
+# --------------------------------------------------------------- HIP graph capture
+@pytest.mark.parametrize("form,R", [("fused", 14), ("pipelined", 14), ("fused", 37)])
+def test_detect_replays_from_a_captured_graph(form, R):
+    """fpcg_detect enqueues only kernels (no allocation, no host sync, no
+    memset node), so it can be captured into a HIP graph.  The graph is
+    replayed several times with eager launches and synchronisations between;
+    every replay must equal the eager result bitwise."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    _say(f"case graph capture form={form} R={R}")
+    wl = _wl(600, 128, 32, R, 64, 20.0, 0.5, 41)
+    dev = torch.device("cuda:0")
+    Ht = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Yt = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    st = torch.from_numpy(wl.sigma2).to(dev)
+    ctx = fp.Context(0)
+    ctx.set_launch_form(form)
+    B, K = Ht.shape[0], Ht.shape[2]
+    out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
+           torch.empty((B,), dtype=torch.int32, device=dev))
+    x0, l0, f0 = fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, ctx=ctx)
+    torch.cuda.synchronize()
+    ref = (x0.cpu().numpy().view(np.uint8), l0.cpu().numpy(), f0.cpu().numpy())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):                      # warm-up on the capture stream
+        fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, ctx=ctx, out=out,
+                  stream=torch.cuda.current_stream())
+    for rep in range(3):
+        for o in out:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (out[0].cpu().numpy().view(np.uint8), out[1].cpu().numpy(), out[2].cpu().numpy())
+        assert all(np.array_equal(a, b) for a, b in zip(got, ref)), f"replay {rep} differs"
+        xe, _, _ = fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, ctx=ctx)   # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(xe.cpu().numpy().view(np.uint8), ref[0])
+    ctx.close()
+
+
+def test_autotuned_launch_matches_explicit_forms():
+    """fpcg_autotune picks one of the built forms for the shape class; the
+    launch in the "auto" form afterwards gives the fused form's bits."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    _say("case autotune c2 shape, fp16 L=4 symmetric")
+    ctx = fp.Context(0)
+    choice = ctx.autotune(2048, 128, 32, 14, 64, 11, 4, "fp16", variant=2, reps=3)
+    _say(f"  chosen form: {choice}")
+    assert choice in ("fused", "pipelined")
+    wl = _wl(300, 128, 32, 14, 64, 20.0, 0.5, 43)
+    dev = torch.device("cuda:0")
+    Ht = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Yt = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    st = torch.from_numpy(wl.sigma2).to(dev)
+    xa, la, fa = fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, ctx=ctx)
+    ctx.set_launch_form("fused")
+    xb, lb, fb = fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, ctx=ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(xa.cpu().numpy().view(np.uint8), xb.cpu().numpy().view(np.uint8))
+    assert np.array_equal(la.cpu().numpy(), lb.cpu().numpy()) and np.array_equal(fa.cpu().numpy(), fb.cpu().numpy())
+    ctx.close()
