@@ -119,6 +119,97 @@ def write_traffic(args, fetch_csv, write_csv):
     log(f"wrote {path}: {rec['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch")
 
 
+def serve_bench(args, n_pool=24, n_requests=400, seed=5):
+    """Requests with (Nbs, K) uniform over the built pairs with K <= Nbs/2,
+    1..1200 channels of 14 received vectors, correlation U[0, 0.9], SNR
+    U[5, 25] dB, each detected by FP-BJ-CG (L = 4, symmetric form) in the format
+    the precision heuristic picks for its class, I = 12.  A pool of distinct
+    requests is drawn once and reused; arrivals are Poisson at a fraction of
+    the loop's measured peak channel rate; latency = completion - arrival."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+    from paper_2504_09820_amd import precision
+
+    rng = np.random.default_rng(seed)
+    pairs = [(n, k) for n in (64, 128, 256) for k in (8, 16, 32, 64) if k <= n // 2]
+    pool = []
+    t0 = time.time()
+    fmt_cache = {}
+    for i in range(n_pool):
+        Nbs, K = pairs[rng.integers(len(pairs))]
+        B = int(rng.integers(1, 1201))
+        zeta = float(rng.uniform(0, 0.9))
+        wl = W.draw(B, Nbs, K, 14, 64, float(rng.uniform(5, 25)), zeta, zeta, seed=9000 + i)
+        key = (Nbs, K, round(zeta, 1))
+        if key not in fmt_cache:
+            fmt_cache[key] = precision.choose_format(K, precision.expected_kappa(wl.H, wl.sigma2, 4, sample=16))[0]
+        pool.append(dict(H=wl.H.astype(np.complex64), Y=wl.Y.astype(np.complex64), s2=wl.sigma2, B=B, K=K, Nbs=Nbs,
+                         sched=fmt_cache[key]))
+    log(f"serving pool: {n_pool} requests drawn in {time.time() - t0:.1f} s; formats "
+        f"{sorted(set(p['sched'] for p in pool))}")
+    ctx = fp.Context(0)
+    srv = fp.Server(ctx, n_slots=8, queue_cap=n_requests + 8)
+
+    def submit(p):
+        return srv.submit(p["H"], p["Y"], p["s2"], 64, 12, 4, p["sched"], variant=2)
+
+    def wait_all(tickets):
+        left = dict(tickets)
+        done = {}
+        while left:
+            for t in list(left):
+                if srv.poll(t) is not None:
+                    done[t] = time.perf_counter()
+                    del left[t]
+        return done
+
+    # peak: everything submitted at once
+    for p in pool[:8]:
+        wait_all({submit(p): 0})                     # warm-up (allocations, first launches)
+    t1 = time.perf_counter()
+    tk = {submit(p): 0 for p in pool}
+    wait_all(tk)
+    peak = sum(p["B"] for p in pool) / (time.perf_counter() - t1)
+    log(f"peak channel rate {peak:.4g} channels/s ({peak * 14:.4g} detections/s)")
+    mean_b = float(np.mean([p["B"] for p in pool]))
+    results = []
+    for load in (0.5, 0.8, 0.95):
+        rate = load * peak / mean_b                  # requests per second
+        gaps = rng.exponential(1.0 / rate, size=n_requests)
+        order = rng.integers(0, n_pool, size=n_requests)
+        arrive, finish, chans = {}, {}, 0
+        start = time.perf_counter()
+        nxt = start
+        pending = {}
+        i = 0
+        while i < n_requests or pending:
+            now = time.perf_counter()
+            while i < n_requests and now >= nxt:
+                p = pool[order[i]]
+                t = submit(p)
+                arrive[t] = nxt
+                pending[t] = True
+                chans += p["B"]
+                nxt += gaps[i]
+                i += 1
+            for t in list(pending):
+                if srv.poll(t) is not None:
+                    finish[t] = time.perf_counter()
+                    del pending[t]
+        wall = time.perf_counter() - start
+        lat = np.array([finish[t] - arrive[t] for t in finish]) * 1e3
+        res = {"offered_load": load, "requests": n_requests, "p50_ms": round(float(np.median(lat)), 3),
+               "p99_ms": round(float(np.quantile(lat, 0.99)), 3), "detections_per_s": round(chans * 14 / wall, 1)}
+        log(f"load {load}: {res}")
+        results.append(res)
+    srv.close()
+    ctx.close()
+    print(json.dumps({"serving": results, "peak_detections_per_s": round(peak * 14, 1), "pool": n_pool,
+                      "method": "FP-BJ-CG L=4 symmetric, heuristic format per class, I=12", "slots": 8}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +224,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: the given schedule, L and iterations only, plus a 1 GiB copy")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: Poisson arrivals of mixed-shape requests through the continuous-batching "
+                         "loop; p50/p99 request latency and throughput at several offered loads")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs of a --profile run (FETCH_SIZE, then WRITE_SIZE) "
                          "into the HBM-traffic record bench.py reports, then exit")
@@ -140,6 +234,10 @@ def main():
 
     if args.traffic_from:
         write_traffic(args, *args.traffic_from)
+        return
+
+    if args.serve and args.gpus == 1:
+        serve_bench(args)
         return
 
     if args.gpus != 1:
