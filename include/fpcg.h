@@ -42,7 +42,7 @@ typedef enum {
     FPCG_E_INVAL = -1,        /* bad argument (null pointer, size, order, L not dividing K, ...) */
     FPCG_E_NOMEM = -2,        /* request does not fit the context's device-memory budget        */
     FPCG_E_DEVICE = -3,       /* a HIP runtime call failed                                      */
-    FPCG_E_UNSUPPORTED = -4,  /* valid but not built (e.g. K > 64, schedule combination)        */
+    FPCG_E_UNSUPPORTED = -4,  /* valid but not built (e.g. K > 128, schedule combination)       */
     FPCG_E_BUSY = -5          /* serving queue full                                             */
 } fpcg_status;
 
@@ -147,10 +147,14 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  * matrix cores, block-Jacobi setup, `iters` (P)CG iterations, optional FP64
  * refresh / refinement, QAM slicer.  One fused kernel; nothing but inputs
  * and outputs touches device memory.
- *   B >= 0 channels (B = 0 is a no-op); Nbs >= 1; 1 <= K <= 64; R >= 1.
+ *   B >= 0 channels (B = 0 is a no-op); Nbs >= 1; 1 <= K <= 128; R >= 1.
  *   qam_order in {4, 16, 64, 256}; iters >= 0 (0 gives x_hat = 0).
- *   block_L = 0: Alg. 2 (no preconditioner); block_L in {4, 8}: Alg. 3,
- *   block_L must divide K and be <= the padded K / 4.
+ *   block_L = 0: Alg. 2 (no preconditioner); block_L in {4, 8, 16}: Alg. 3,
+ *   block_L must divide K; each lane of the kernel owns whole Jacobi blocks,
+ *   so L <= 8 below K = 65 and L = 16 runs the K <= 128 build.
+ *   65 <= K <= 128 is built for fp8, fp16 and bf16 operands, left block-Jacobi
+ *   forms (variant 0 or 1) and no FP64 refresh; with fp8 also with FP64
+ *   refinement.  Other combinations return FPCG_E_UNSUPPORTED.
  *   sched = NULL means the all-FP64 schedule.
  *   flags may be NULL.
  */

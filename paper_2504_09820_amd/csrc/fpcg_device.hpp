@@ -45,6 +45,12 @@ __device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
     return __builtin_amdgcn_cvt_f32_fp8((int)byte, 0);
 }
 
+// one element rounded to an operand format, as the bits that format stores
+template <int FMT> __device__ __forceinline__ uint32_t op_bits(float v);
+template <> __device__ __forceinline__ uint32_t op_bits<F8>(float v) { return fp8x2_bits(v, 0.f) & 0xffu; }
+template <> __device__ __forceinline__ uint32_t op_bits<F16>(float v) { return f16_bits(v); }
+template <> __device__ __forceinline__ uint32_t op_bits<BF16>(float v) { return bf16_bits(v); }
+
 // fmt(v): the value v rounded to fmt and widened back to fp32
 __device__ __forceinline__ float round_to(float v, int fmt) {
     switch (fmt) {

@@ -72,7 +72,13 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     // A operand: registers when small, else fragment-ordered LDS copy (reduced
     // precision) or read in place from the u_W Gram (fp32 / fp64)
     static constexpr bool AREG = LOWP ? (NAV * (int)sizeof(frag) <= 128) : (NAV * (int)sizeof(Wt) <= 256);
-    static constexpr bool AFRAG_LDS = LOWP && !AREG;
+    // K = 128: the u_W Gram does not fit LDS next to everything else, so A is
+    // kept only in the operand format, row-major (and its diagonal blocks in
+    // u_W for the block-Jacobi setup); built for the reduced formats, left form
+    static constexpr bool AROW = KP >= 128;
+    static_assert(!AROW || LOWP, "K = 128 keeps A in a reduced operand format");
+    static constexpr bool AFRAG_LDS = LOWP && !AREG && !AROW;
+    static constexpr size_t ESZ = (FMT == F8) ? 1 : 2;   // bytes of one operand element (AROW)
     static constexpr int NPAIR = F * (F + 1) / 2;
     static constexpr int PPW = (NPAIR + NW - 1) / NW;
     static constexpr int MFPW = (F + NW - 1) / NW;
@@ -84,9 +90,10 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr int MIN_WAVES = (KP <= 32 && FMT != F64) ? 3 : 1;
     // LDS layout in bytes: [Ar | Ai | Br | Bi | M | F | S | X | X64]
     static constexpr size_t W = sizeof(Wt);
+    static constexpr size_t sz_Aplane = AROW ? (size_t)KP * KP * ESZ : W * KP * LDA;
     static constexpr size_t off_Ar = 0;
-    static constexpr size_t off_Ai = off_Ar + W * KP * LDA;
-    static constexpr size_t off_Br = off_Ai + W * KP * LDA;
+    static constexpr size_t off_Ai = off_Ar + sz_Aplane;
+    static constexpr size_t off_Br = off_Ai + sz_Aplane;
     static constexpr size_t off_Bi = off_Br + W * KP * 16;
     static constexpr size_t off_M = off_Bi + W * KP * 16;
     static constexpr size_t sz_M = LB ? 2 * W * KP * LB : 0;           // M_d or T blocks
@@ -95,7 +102,9 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr size_t off_S = off_F + sz_F;                       // scratch: BJ factors or exchange
     // BJ setup scratch: T = C^{-1} for the left form before M = T^H T (the
     // symmetric form writes T straight into M)
-    __host__ __device__ static constexpr size_t sz_bj(bool split) { return (LB && !split) ? 2 * W * KP * LB : 0; }
+    __host__ __device__ static constexpr size_t sz_bj(bool split) {
+        return (LB && !split) ? (LB > 8 ? 4 : 2) * W * KP * LB : 0;   // L = 16 also exchanges C here
+    }
     static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * 8 : 0;    // p exchange (doubles)
     static constexpr size_t sz_red = (NW > 1) ? (size_t)2 * NW * 16 * 4 * 8 : 0;    // dot partials, 2 parities
     static constexpr size_t sz_ref = (NW > 1) ? (size_t)NW * RC * 16 * 2 * 8 : 0;   // refinement partials
@@ -104,7 +113,9 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     __host__ __device__ static constexpr size_t off_X(bool split) { return off_S + sz_S(split); }   // x slots [2][SH][NT]
     static constexpr size_t sz_X = 2 * W * SH * NT;
     static constexpr size_t sz_X64 = 2 * 8 * (size_t)SH * NT;           // FP64 iterate [2][SH][NT]
-    static_assert(sz_X <= 2 * W * KP * LDA, "x fits the Gram's slot");
+    // AROW: the u_W diagonal blocks live in the x slot until the solve starts
+    static_assert(!AROW || sz_X >= 2 * W * KP * (LB ? LB : 1), "diagonal blocks fit the x slot");
+    static_assert(AROW || sz_X <= 2 * W * KP * LDA, "x fits the Gram's slot");
     static constexpr size_t sz_B = 2 * W * KP * 16;
     static constexpr bool B_FITS = sz_X + sz_B <= 2 * W * KP * LDA;   // x and B in the Gram's slot
     // Once A sits in registers and no FP64 refresh reads the stored Gram, the
@@ -230,6 +241,11 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
 
     // B carried in registers (compact layout), stored once A is packed
     Wt bcr[C::MFPW][4], bci[C::MFPW][4];
+    int eA = 0;                                       // fp8: exponent of the iteration matrix's scale
+    unsigned char* sA8r = sbuf + C::off_Ar;           // AROW: A in the operand format, row-major
+    unsigned char* sA8i = sbuf + C::off_Ai;
+    Wt* sDr = reinterpret_cast<Wt*>(spriv + C::off_X(false));   // AROW: u_W diagonal blocks (x slot)
+    Wt* sDi = sDr + KP * (LB ? LB : 1);
     if constexpr (MODE != MODE_SOLVE) {
     // ------------------------------------------------------------ fp8 scales
     int eH = 0, eY = 0;
@@ -325,6 +341,78 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         const Wt invH = (Wt)ldexpf(1.f, -eH), invY = (Wt)ldexpf(1.f, -eY);
         const Wt s2w = (Wt)s2;
         bool bad = false;
+        // the u_W value of one Gram element (sigma^2 on the diagonal, padding diagonal 1)
+        auto gram_at = [&](int s, int jj, int row, int cc, Wt& ar, Wt& ai) {
+            ar = (Wt)gAr[s][jj];
+            ai = (Wt)gAi[s][jj];
+            if constexpr (FMT == F8) { ar = ar * invH * invH; ai = ai * invH * invH; }
+            if (row == cc) {
+                ai = 0;
+                ar = (row < K) ? ar + s2w : (Wt)1;
+            }
+        };
+        if constexpr (C::AROW) {
+            // largest magnitude first (fp8 scale), then the operand-format bits of
+            // both triangles and the u_W diagonal blocks; padding entries are zero
+            // in the operand so that they contribute exactly nothing to A p
+            float amax = 0.f;
+            int q = 0;
+#pragma unroll
+            for (int f1 = 0; f1 < F; ++f1)
+#pragma unroll
+                for (int f2 = f1; f2 < F; ++f2) {
+                    if (NW == 1 || q % NW == wave) {
+                        const int s = q / NW;
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const int row = 16 * f1 + OG::crow(g, jj), cc = 16 * f2 + n;
+                            Wt ar, ai;
+                            gram_at(s, jj, row, cc, ar, ai);
+                            bad |= !__builtin_isfinite(ar) || !__builtin_isfinite(ai);
+                            if (row < K && cc < K) amax = fmaxf(amax, fmaxf(fabsf((float)ar), fabsf((float)ai)));
+                        }
+                    }
+                    ++q;
+                }
+            if constexpr (FMT == F8) eA = fp8_scale_exp(block_max(amax));
+            const float sAs = ldexpf(1.f, eA);
+            auto put = [&](unsigned char* base, int idx, float v) {
+                const uint32_t b = op_bits<FMT>(v);
+                if constexpr (C::ESZ == 1) base[idx] = (unsigned char)b;
+                else reinterpret_cast<uint16_t*>(base)[idx] = (uint16_t)b;
+            };
+            q = 0;
+#pragma unroll
+            for (int f1 = 0; f1 < F; ++f1)
+#pragma unroll
+                for (int f2 = f1; f2 < F; ++f2) {
+                    if (NW == 1 || q % NW == wave) {
+                        const int s = q / NW;
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const int row = 16 * f1 + OG::crow(g, jj), cc = 16 * f2 + n;
+                            Wt ar, ai;
+                            gram_at(s, jj, row, cc, ar, ai);
+                            const bool real_entry = row < K && cc < K;
+                            const float vr = real_entry ? (float)ar * sAs : 0.f;
+                            const float vi = real_entry ? (float)ai * sAs : 0.f;
+                            put(sA8r, row * KP + cc, vr);
+                            put(sA8i, row * KP + cc, vi);
+                            if (f1 != f2) {
+                                put(sA8r, cc * KP + row, vr);
+                                put(sA8i, cc * KP + row, -vi);
+                            }
+                            if constexpr (LB > 0) {
+                                if (row / LB == cc / LB) {
+                                    sDr[row * LB + cc % LB] = ar;
+                                    sDi[row * LB + cc % LB] = ai;
+                                }
+                            }
+                        }
+                    }
+                    ++q;
+                }
+        } else {
         int q = 0;
 #pragma unroll
         for (int f1 = 0; f1 < F; ++f1) {
@@ -352,6 +440,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 }
                 ++q;
             }
+        }
         }
 #pragma unroll
         for (int f = 0; f < F; ++f) {
@@ -401,19 +490,23 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         // operations in the same order, so identical results): no exchange.
         // Lower triangle of A_blk; the Cholesky factor C overwrites it, with
         // 1 / c_jj kept in the (otherwise zero) imaginary slot of the diagonal.
+        // element (r, c) of this block of the u_W Gram
+        auto blk = [&](int r, int c, Wt& re, Wt& im) {
+            if constexpr (C::AROW) { re = sDr[(cb + r) * LB + c]; im = sDi[(cb + r) * LB + c]; }
+            else { re = sAr[(cb + r) * LDA + cb + c]; im = sAi[(cb + r) * LDA + cb + c]; }
+        };
+        Wt diag = 0;                                  // a_ii, for the not-PD fallback
+        bool blk_bad = false;
+        Wt tr[LB], ti[LB];
+        if constexpr (LB <= 8) {
         Wt cr[LB][LB], ci[LB][LB];
 #pragma unroll
         for (int r = 0; r < LB; ++r)
 #pragma unroll
-            for (int c = 0; c <= r; ++c) {
-                cr[r][c] = sAr[(cb + r) * LDA + cb + c];
-                ci[r][c] = sAi[(cb + r) * LDA + cb + c];
-            }
-        Wt diag = 0;                                  // a_ii, for the not-PD fallback
+            for (int c = 0; c <= r; ++c) blk(r, c, cr[r][c], ci[r][c]);
 #pragma unroll
         for (int r = 0; r < LB; ++r)
             if (r == i) diag = cr[r][r];
-        bool blk_bad = false;
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
             Wt d = cr[j][j];
@@ -434,7 +527,6 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         }
         // T = C^{-1}: this lane forms column i by forward substitution;
         // t_m = 0 for m < i, so full-length sums add exact zeros
-        Wt tr[LB], ti[LB];
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
             const Wt inv_rr = ci[r][r];
@@ -446,6 +538,64 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             }
             tr[r] = (r == i) ? inv_rr : (r > i ? -sr * inv_rr : (Wt)0);
             ti[r] = (r > i) ? -si * inv_rr : (Wt)0;
+        }
+        } else {
+        // L = 16: a whole block does not fit one lane's registers.  Lane i owns
+        // row i of the block; C is exchanged through LDS (the imaginary
+        // diagonal slot again holding 1 / c_jj), one column per step.
+        Wt* sLr = sTr + 2 * KP * LB;                  // after the T scratch
+        Wt* sLi = sLr + KP * LB;
+        Wt ar[LB], ai[LB];
+#pragma unroll
+        for (int c = 0; c < LB; ++c) blk(i, c, ar[c], ai[c]);
+#pragma unroll
+        for (int c = 0; c < LB; ++c)
+            if (c == i) diag = ar[c];
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            if (act && i == j) {
+                Wt d = ar[j];
+                if (!(d > 0) || !__builtin_isfinite(d)) { bad = true; d = 1; }
+                const Wt l = sqrt(d);
+                sLr[(cb + j) * LB + j] = l;
+                sLi[(cb + j) * LB + j] = (Wt)1 / l;
+            }
+            bsync();
+            const Wt inv = sLi[(cb + j) * LB + j];
+            const Wt lr = ar[j] * inv, li = ai[j] * inv;
+            if (act && i > j) {
+                sLr[(cb + i) * LB + j] = lr;
+                sLi[(cb + i) * LB + j] = li;
+            }
+            bsync();
+            if (i > j) {
+                Wt kr[LB], ki[LB];
+#pragma unroll
+                for (int k = j + 1; k < LB; ++k) { kr[k] = sLr[(cb + k) * LB + j]; ki[k] = sLi[(cb + k) * LB + j]; }
+#pragma unroll
+                for (int k = j + 1; k < LB; ++k) {   // a_ik -= l_ij conj(l_kj), needed for k <= i
+                    ar[k] = fma(-lr, kr[k], fma(-li, ki[k], ar[k]));
+                    ai[k] = fma(-li, kr[k], fma(lr, ki[k], ai[k]));
+                }
+            }
+        }
+        // the block's lanes are one aligned group of LB lanes of a wave
+        const uint64_t bal = __ballot(act && bad);
+        blk_bad = ((bal >> (lane & ~(LB - 1))) & ((LB == 64) ? ~0ull : ((1ull << LB) - 1))) != 0;
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const Wt inv_rr = sLi[(cb + r) * LB + r];
+            Wt sr = 0, si = 0;
+#pragma unroll
+            for (int m = 0; m < r; ++m) {
+                const Wt cr_ = sLr[(cb + r) * LB + m], ci_ = sLi[(cb + r) * LB + m];
+                sr = fma(cr_, tr[m], fma(-ci_, ti[m], sr));
+                si = fma(cr_, ti[m], fma(ci_, tr[m], si));
+            }
+            tr[r] = (r == i) ? inv_rr : (r > i ? -sr * inv_rr : (Wt)0);
+            ti[r] = (r > i) ? -si * inv_rr : (Wt)0;
+        }
         }
         if (blk_bad) {
             // not positive definite: T = diag(a_ii)^{-1/2}, so M_d = diag(a_ii)^{-1}
@@ -581,8 +731,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     };
 
     // ------------------------------------------------------------ fp8 scale of the u_MV matrix
-    int eA = 0;
-    if constexpr (FMT == F8) {
+    if constexpr (FMT == F8 && !C::AROW) {            // (AROW: taken from the Gram accumulators)
         float ma = 0.f;
         for (int i = tid; i < K * K; i += NT) {
             const int r = i / K, c = i % K;
@@ -658,6 +807,10 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             return afr[fidx(phi, ws, kb, ri)];
         } else if constexpr (C::AFRAG_LDS) {
             return sF[fidx(phi, ws, kb, ri) * NT + tid];
+        } else if constexpr (C::AROW) {
+            // KPL consecutive contraction values of one row: one aligned LDS read
+            const unsigned char* base = ri ? sA8i : sA8r;
+            return *reinterpret_cast<const frag*>(base + ((size_t)rowc(phi) * KP + colc(ws, kb, 0)) * C::ESZ);
         } else {
             Wt re, im;
             a_at(rowc(phi), colc(ws, kb, 0), re, im);
@@ -1038,7 +1191,8 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 }
             }
             // ---- FP64 residual refresh on the stored Gram (A, or T A T^H)
-            if (P.refresh_every > 0 && it % P.refresh_every == 0 && it < P.iters) {
+            // (not built for AROW: no u_W Gram is kept; refused on the host)
+            if (!C::AROW && P.refresh_every > 0 && it % P.refresh_every == 0 && it < P.iters) {
                 if constexpr (NW > 1) __syncthreads();   // x of every wave visible
                 f64x4 Rr[NF], Ri[NF];
 #pragma unroll

@@ -45,6 +45,8 @@ static std::vector<KernelEntry>& table() {
         register_bf16(t);
         register_f16(t);
         register_f8(t);
+        register_k128_f8(t);
+        register_k128_f16(t);
     });
     return t;
 }
@@ -57,7 +59,7 @@ static const KernelEntry* find_entry(int KP, int FMT, int LB, int io_c64) {
 
 // smallest padded K with a compiled variant for (K, fmt, L)
 static int pick_kp(int K, int FMT, int L) {
-    static const int kps[] = {16, 32, 64};
+    static const int kps[] = {16, 32, 64, 128};
     for (int kp : kps) {
         if (kp < K) continue;
         const int sh = kp / (4 * waves_for(kp, FMT));
@@ -95,14 +97,20 @@ fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
     const int want_work = s->mv_op == FPCG_F64 ? FPCG_F64 : FPCG_F32;
     if (s->work != want_work || s->ip != want_work)
         return fail(FPCG_E_UNSUPPORTED, "work and ip must be %s for mv_op %d", want_work == FPCG_F64 ? "F64" : "F32", s->mv_op);
-    if (K > 64) return fail(FPCG_E_UNSUPPORTED, "K=%d > 64 is not built", K);
-    if (L != 0 && L != 4 && L != 8) return fail(FPCG_E_UNSUPPORTED, "block_L=%d not built (0, 4, 8)", L);
+    if (K > 128) return fail(FPCG_E_UNSUPPORTED, "K=%d > 128 is not built", K);
+    if (L != 0 && L != 4 && L != 8 && L != 16) return fail(FPCG_E_UNSUPPORTED, "block_L=%d not built (0, 4, 8, 16)", L);
     // map the public format enum to the kernel enum (identical values)
     const int fmt = s->mv_op;
     const int kp = pick_kp(K, fmt, L);
     if (!kp) return fail(FPCG_E_UNSUPPORTED, "no variant for K=%d fmt=%d L=%d", K, fmt, L);
     {
         const KernelEntry* e = find_entry(kp, fmt, L, 1);   // the layout does not depend on the I/O type
+        const int sp = (L > 0 && s->variant == 2) ? 1 : 0, ref = s->refine_steps > 0 ? 1 : 0;
+        if (e->arow && s->refresh_every > 0)
+            return fail(FPCG_E_UNSUPPORTED, "K=%d: the FP64 refresh needs the u_W Gram, kept only for K <= 64", K);
+        if (!e->fn[sp][ref])
+            return fail(FPCG_E_UNSUPPORTED, "K=%d: %s%s not built for this format", K,
+                        sp ? "the symmetric block-Jacobi form" : "this form", ref ? " with refinement" : "");
         const size_t lds = e->lds(L > 0 && s->variant == 2, s->refine_steps > 0, s->refresh_every);
         if (lds > 160 * 1024)
             return fail(FPCG_E_UNSUPPORTED, "this schedule at K=%d needs %zu bytes of LDS (160 KiB per workgroup)", K, lds);
@@ -192,7 +200,7 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
         for (const auto& t : table())
             for (int sp = 0; sp < 2; ++sp)
                 for (int r = 0; r < 2; ++r)
-                    if (t.lds(sp != 0, r != 0, 1) > 65536)   // the largest layout of that build
+                    if (t.fn[sp][r] && t.lds(sp != 0, r != 0, 1) > 65536)   // the largest layout of that build
                         (void)hipFuncSetAttribute(t.fn[sp][r], hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   (int)t.lds(sp != 0, r != 0, 1));
     });

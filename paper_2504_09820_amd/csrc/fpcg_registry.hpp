@@ -11,6 +11,7 @@ namespace fpcg {
 
 struct KernelEntry {
     int KP, NW, FMT, LB, io_c64;
+    int arow = 0;               // A kept only in the operand format (no u_W Gram in LDS)
     size_t (*lds)(bool split, bool refine, int refresh_every);   // dynamic LDS bytes of a launch
     // builds of the kernel: [symmetric block-Jacobi form][FP64 refinement]
     const void* fn[2][2];
@@ -26,11 +27,13 @@ void register_f32(std::vector<KernelEntry>& v);
 void register_bf16(std::vector<KernelEntry>& v);
 void register_f16(std::vector<KernelEntry>& v);
 void register_f8(std::vector<KernelEntry>& v);
+void register_k128_f8(std::vector<KernelEntry>& v);
+void register_k128_f16(std::vector<KernelEntry>& v);
 
 // waves per channel for a padded K and operand format: one wave holds the
 // whole iterate (K/4 complex entries per lane) except where the FP64 vectors
-// would not fit the register file
-constexpr int waves_for(int KP, int FMT) { return (FMT == F64 && KP >= 64) ? 2 : 1; }
+// would not fit the register file, and at K = 128 (two waves, K/8 entries)
+constexpr int waves_for(int KP, int FMT) { return ((FMT == F64 && KP >= 64) || KP >= 128) ? 2 : 1; }
 
 template <int KP, int NW, int FMT, int LB, bool SP, bool RF, typename IOT>
 void set_build(KernelEntry& e) {
@@ -48,12 +51,18 @@ void add_entry(std::vector<KernelEntry>& v) {
     KernelEntry e;
     e.KP = KP; e.NW = NW; e.FMT = FMT; e.LB = LB;
     e.io_c64 = sizeof(IOT) == 4 ? 1 : 0;
+    e.arow = C::AROW ? 1 : 0;
     e.lds = [](bool sp, bool r, int f) -> size_t { return C::lds(LB > 0 && sp, r, f); };
     set_build<KP, NW, FMT, LB, false, false, IOT>(e);
-    set_build<KP, NW, FMT, LB, false, true, IOT>(e);
-    if constexpr (LB > 0) {
+    // refinement builds only where their LDS layout fits (160 KiB)
+    if constexpr (C::lds_general(false, true, 0) <= 160 * 1024) set_build<KP, NW, FMT, LB, false, true, IOT>(e);
+    else { e.fn[0][1] = nullptr; e.launch[0][1] = nullptr; }
+    if constexpr (LB > 0 && !C::AROW) {               // the symmetric form needs the u_W Gram in LDS
         set_build<KP, NW, FMT, LB, true, false, IOT>(e);
         set_build<KP, NW, FMT, LB, true, true, IOT>(e);
+    } else if constexpr (LB > 0) {
+        e.fn[1][0] = e.fn[1][1] = nullptr;
+        e.launch[1][0] = e.launch[1][1] = nullptr;
     } else {
         e.fn[1][0] = e.fn[0][0]; e.fn[1][1] = e.fn[0][1];
         e.launch[1][0] = e.launch[0][0]; e.launch[1][1] = e.launch[0][1];
