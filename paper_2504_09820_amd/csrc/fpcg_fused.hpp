@@ -368,7 +368,11 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                             const int row = 16 * f1 + OG::crow(g, jj), cc = 16 * f2 + n;
                             Wt ar, ai;
                             gram_at(s, jj, row, cc, ar, ai);
-                            bad |= !__builtin_isfinite(ar) || !__builtin_isfinite(ai);
+                            const bool nf = !__builtin_isfinite(ar) || !__builtin_isfinite(ai);
+                            bad |= nf;
+                            if constexpr (FMT == F8) {
+                                if (nf && row < K && cc < K) myflag |= FLAG_FP8_SAT;
+                            }
                             if (row < K && cc < K) amax = fmaxf(amax, fmaxf(fabsf((float)ar), fabsf((float)ai)));
                         }
                     }
@@ -731,14 +735,18 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     };
 
     // ------------------------------------------------------------ fp8 scale of the u_MV matrix
+    // (a non-finite entry leaves the fp8 operand non-finite: FP8_SAT, as NONFINITE)
     if constexpr (FMT == F8 && !C::AROW) {            // (AROW: taken from the Gram accumulators)
         float ma = 0.f;
+        bool nf = false;
         for (int i = tid; i < K * K; i += NT) {
             const int r = i / K, c = i % K;
             Wt re, im;
             a_at(r, c, re, im);
             ma = fmaxf(ma, fmaxf(fabsf((float)re), fabsf((float)im)));
+            nf |= !__builtin_isfinite(re) || !__builtin_isfinite(im);
         }
+        if (nf) myflag |= FLAG_FP8_SAT;
         ma = block_max(ma);
         eA = fp8_scale_exp(ma);
     }

@@ -226,7 +226,7 @@ def test_breakdown_and_nonfinite_channels_are_isolated():
     Y = wl.Y.copy()
     Y[1] = 0
     H[3, 2, 5] = np.nan
-    for sched, io in (("fp64", np.complex128), ("bf16", np.complex64), ("fp32", np.complex64)):
+    for sched, io in (("fp64", np.complex128), ("bf16", np.complex64), ("fp32", np.complex64), ("fp8", np.complex64)):
         _say(f"case isolation {sched}")
         x, lab, fl = gpu_detect(wl, 16, 8, 4, sched, io, H=H, Y=Y)
         assert np.all(x[1] == 0) and (fl[1] & 2)
@@ -238,6 +238,34 @@ def test_breakdown_and_nonfinite_channels_are_isolated():
         assert np.array_equal(x[keep], x2) and np.array_equal(lab[keep], lab2) and np.array_equal(fl[keep], fl2)
         ref = oracle_detect(wl, 16, 8, 4, sched, io, H=H, Y=Y)
         assert np.array_equal(fl, ref.flags.astype(np.int64))
+
+
+@pytest.mark.parametrize("K,L,sched,form", [(128, 16, "fp8", "fused"), (32, 4, "fp16", "pipelined"),
+                                            (32, 8, "fp8", "fused")])
+def test_nonfinite_and_zero_channels_at_other_shapes(K, L, sched, form):
+    """A NaN in one channel's H and an all-zero Y in another flag exactly
+    those channels (as the oracle does) and leave the rest untouched."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    _say(f"case isolation K={K} L={L} {sched} {form}")
+    wl = _wl(5, 4 * K, K, 5, 16, 15.0, 0.3, 8)
+    H = wl.H.copy()
+    Y = wl.Y.copy()
+    Y[1] = 0
+    H[3, 2, 5] = np.nan
+    ctx = fp.Context(0)
+    ctx.set_launch_form(form)
+    dev = torch.device("cuda:0")
+    x, lab, fl = fp.detect(torch.from_numpy(H.astype(np.complex64)).to(dev), torch.from_numpy(Y.astype(np.complex64)).to(dev),
+                           torch.from_numpy(wl.sigma2).to(dev), 16, 8, L, sched, ctx=ctx)
+    torch.cuda.synchronize()
+    x, fl = x.cpu().numpy(), fl.cpu().numpy().astype(np.int64)
+    ref = oracle_detect(wl, 16, 8, L, sched, np.complex64, H=H, Y=Y)
+    assert np.array_equal(fl, ref.flags.astype(np.int64)), (fl, ref.flags)
+    assert np.all(x[1] == 0) and np.all(x[3] == 0)
+    ctx.close()
 
 
 def test_run_to_run_bitwise_determinism():
