@@ -152,9 +152,6 @@ def serve_bench(args, n_pool=24, n_requests=400, seed=5):
     ctx = fp.Context(0)
     srv = fp.Server(ctx, n_slots=8, queue_cap=n_requests + 8)
 
-    def submit(p):
-        return srv.submit(p["H"], p["Y"], p["s2"], 64, 12, 4, p["sched"], variant=2)
-
     def wait_all(tickets):
         left = dict(tickets)
         done = {}
@@ -165,48 +162,56 @@ def serve_bench(args, n_pool=24, n_requests=400, seed=5):
                     del left[t]
         return done
 
-    # peak: everything submitted at once
-    for p in pool[:8]:
-        wait_all({submit(p): 0})                     # warm-up (allocations, first launches)
-    t1 = time.perf_counter()
-    tk = {submit(p): 0 for p in pool}
-    wait_all(tk)
-    peak = sum(p["B"] for p in pool) / (time.perf_counter() - t1)
-    log(f"peak channel rate {peak:.4g} channels/s ({peak * 14:.4g} detections/s)")
-    mean_b = float(np.mean([p["B"] for p in pool]))
-    results = []
-    for load in (0.5, 0.8, 0.95):
-        rate = load * peak / mean_b                  # requests per second
-        gaps = rng.exponential(1.0 / rate, size=n_requests)
-        order = rng.integers(0, n_pool, size=n_requests)
-        arrive, finish, chans = {}, {}, 0
-        start = time.perf_counter()
-        nxt = start
-        pending = {}
-        i = 0
-        while i < n_requests or pending:
-            now = time.perf_counter()
-            while i < n_requests and now >= nxt:
-                p = pool[order[i]]
-                t = submit(p)
-                arrive[t] = nxt
-                pending[t] = True
-                chans += p["B"]
-                nxt += gaps[i]
-                i += 1
-            for t in list(pending):
-                if srv.poll(t) is not None:
-                    finish[t] = time.perf_counter()
-                    del pending[t]
-        wall = time.perf_counter() - start
-        lat = np.array([finish[t] - arrive[t] for t in finish]) * 1e3
-        res = {"offered_load": load, "requests": n_requests, "p50_ms": round(float(np.median(lat)), 3),
-               "p99_ms": round(float(np.quantile(lat, 0.99)), 3), "detections_per_s": round(chans * 14 / wall, 1)}
-        log(f"load {load}: {res}")
-        results.append(res)
+    def sweep(submit, label):
+        for p in pool[:8]:
+            wait_all({submit(p): 0})                 # warm-up (allocations, first launches)
+        t1 = time.perf_counter()
+        wait_all({submit(p): 0 for p in pool})       # peak: everything submitted at once
+        peak = sum(p["B"] for p in pool) / (time.perf_counter() - t1)
+        log(f"{label}: peak channel rate {peak:.4g} channels/s ({peak * 14:.4g} detections/s)")
+        mean_b = float(np.mean([p["B"] for p in pool]))
+        results = []
+        for load in (0.5, 0.8, 0.95):
+            rate = load * peak / mean_b              # requests per second
+            gaps = rng.exponential(1.0 / rate, size=n_requests)
+            order = rng.integers(0, n_pool, size=n_requests)
+            arrive, finish, chans = {}, {}, 0
+            start = time.perf_counter()
+            nxt = start
+            pending = {}
+            i = 0
+            while i < n_requests or pending:
+                now = time.perf_counter()
+                while i < n_requests and now >= nxt:
+                    p = pool[order[i]]
+                    t = submit(p)
+                    arrive[t] = nxt
+                    pending[t] = True
+                    chans += p["B"]
+                    nxt += gaps[i]
+                    i += 1
+                for t in list(pending):
+                    if srv.poll(t) is not None:
+                        finish[t] = time.perf_counter()
+                        del pending[t]
+            wall = time.perf_counter() - start
+            lat = np.array([finish[t] - arrive[t] for t in finish]) * 1e3
+            res = {"offered_load": load, "requests": n_requests, "p50_ms": round(float(np.median(lat)), 3),
+                   "p99_ms": round(float(np.quantile(lat, 0.99)), 3), "detections_per_s": round(chans * 14 / wall, 1)}
+            log(f"{label} load {load}: {res}")
+            results.append(res)
+        return {"peak_detections_per_s": round(peak * 14, 1), "loads": results}
+
+    # requests carrying H, sigma^2 and Y from host memory
+    host = sweep(lambda p: srv.submit(p["H"], p["Y"], p["s2"], 64, 12, 4, p["sched"], variant=2), "host channels")
+    # channels resident on the device (uploaded once), requests carrying Y only
+    for p in pool:
+        p["handle"] = srv.channels(p["H"], p["s2"])
+    resident = sweep(lambda p: srv.submit(None, p["Y"], None, 64, 12, 4, p["sched"], variant=2, channels=p["handle"]),
+                     "resident channels")
     srv.close()
     ctx.close()
-    print(json.dumps({"serving": results, "peak_detections_per_s": round(peak * 14, 1), "pool": n_pool,
+    print(json.dumps({"serving": {"host_channels": host, "resident_channels": resident}, "pool": n_pool,
                       "method": "FP-BJ-CG L=4 symmetric, heuristic format per class, I=12", "slots": 8}))
 
 

@@ -198,15 +198,31 @@ typedef struct {
     int32_t io_c64;
     int32_t qam_order, iters, block_L;
     fpcg_schedule sched;
-    const void* H;        /* host */
+    const void* H;        /* host (ignored when `channels` is set) */
     const void* Y;        /* host */
-    const double* sigma2; /* host */
+    const double* sigma2; /* host (ignored when `channels` is set) */
     void* xhat;           /* host, written on completion */
     uint8_t* labels;      /* host, written on completion */
     uint32_t* flags;      /* host, written on completion (may be NULL) */
+    uint64_t channels;    /* 0, or a channel set from fpcg_server_channels whose
+                             B, Nbs, K and io_c64 match: H and sigma^2 are then
+                             read from device memory, only Y travels */
 } fpcg_request;
 
 typedef struct fpcg_server fpcg_server;
+
+/* Device-resident channel set: H (B, Nbs, K) and sigma2 (B) are copied to the
+ * device once (counted against the context's budget) and stay there until
+ * released, so that requests for the same channels (further received
+ * vectors within a coherence block) carry only Y.  Host buffers may be freed
+ * on return.  FPCG_E_NOMEM if the set does not fit next to what the server
+ * holds; FPCG_E_INVAL for bad sizes or NULL pointers. */
+fpcg_status fpcg_server_channels(fpcg_server* srv, int64_t B, int32_t Nbs, int32_t K, int32_t io_c64,
+                                 const void* H, const double* sigma2, uint64_t* handle);
+
+/* Releases a channel set once no queued or running request uses it
+ * (FPCG_E_BUSY otherwise; FPCG_E_INVAL for an unknown handle). */
+fpcg_status fpcg_server_release(fpcg_server* srv, uint64_t handle);
 
 /* n_slots concurrent streams (1..16), queue_cap pending requests (>= 1). */
 fpcg_status fpcg_server_create(fpcg_ctx* ctx, int32_t n_slots, int32_t queue_cap, fpcg_server** out);
@@ -223,8 +239,9 @@ fpcg_status fpcg_poll(fpcg_server* srv, uint64_t ticket, int32_t* done);
 /* Advance until every submitted request has completed. */
 fpcg_status fpcg_drain(fpcg_server* srv);
 
-/* In-flight requests, queued requests, and device bytes of the server's slot
- * buffers (kept for reuse between requests; never above the budget). */
+/* In-flight requests, queued requests, and device bytes the server holds: its
+ * slot buffers (kept for reuse between requests) and resident channel sets;
+ * never above the budget. */
 fpcg_status fpcg_server_stats(fpcg_server* srv, int32_t* in_flight, int32_t* queued, size_t* bytes_held);
 
 /* Drains, then frees the server. */

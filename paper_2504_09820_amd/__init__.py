@@ -58,6 +58,7 @@ class _Request(ctypes.Structure):
         ("block_L", ctypes.c_int32), ("sched", Schedule),
         ("H", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("sigma2", ctypes.c_void_p),
         ("xhat", ctypes.c_void_p), ("labels", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+        ("channels", ctypes.c_uint64),
     ]
 
 
@@ -84,6 +85,10 @@ def lib():
     L.fpcg_autotune.argtypes = [vp, vp, i64, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Schedule), i32,
                                 ctypes.POINTER(i32)]
     L.fpcg_autotune.restype = st
+    L.fpcg_server_channels.argtypes = [vp, i64, i32, i32, i32, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.fpcg_server_channels.restype = st
+    L.fpcg_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.fpcg_server_release.restype = st
     L.fpcg_strerror.argtypes = [i32]
     L.fpcg_strerror.restype = ctypes.c_char_p
     L.fpcg_last_error.argtypes = []
@@ -266,24 +271,53 @@ class Server:
         self._h = ctypes.c_void_p()
         _check(lib().fpcg_server_create(ctx.handle, n_slots, queue_cap, ctypes.byref(self._h)))
         self._keep = {}
+        self._chans = {}
+
+    def channels(self, H, sigma2):
+        """Upload a channel set (H (B, Nbs, K) complex64/complex128, sigma2 (B,))
+        to the device once; returns a handle for submit(channels=...)."""
+        import numpy as np
+
+        H = np.ascontiguousarray(H)
+        s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
+        B, Nbs, K = H.shape
+        h = ctypes.c_uint64()
+        _check(lib().fpcg_server_channels(self._h, B, Nbs, K, 1 if H.dtype == np.complex64 else 0,
+                                          H.ctypes.data, s2.ctypes.data, ctypes.byref(h)))
+        self._chans[h.value] = (B, Nbs, K, H.dtype)
+        return h.value
+
+    def release(self, handle):
+        _check(lib().fpcg_server_release(self._h, handle))
+        self._chans.pop(handle, None)
 
     def submit(self, H, Y, sigma2, qam, iters, L=0, schedule_: "str | Schedule" = "fp64",
-               refresh_every=0, refine_steps=0, variant=0):
-        """H, Y, sigma2: numpy arrays (complex64/complex128, float64).  Returns a ticket."""
+               refresh_every=0, refine_steps=0, variant=0, channels=None):
+        """H, Y, sigma2: numpy arrays (complex64/complex128, float64); with
+        `channels` (a handle from channels()) H and sigma2 may be None and only
+        Y is sent.  Returns a ticket."""
         import numpy as np
 
         sched = schedule(schedule_, refresh_every, refine_steps, variant) if isinstance(schedule_, str) else schedule_
-        H = np.ascontiguousarray(H)
-        Y = np.ascontiguousarray(Y, dtype=H.dtype)
-        s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
-        B, Nbs, K = H.shape
+        if channels is not None:
+            B, Nbs, K, dt = self._chans[channels]
+            Y = np.ascontiguousarray(Y, dtype=dt)
+            H = s2 = None
+            hp = sp = None
+        else:
+            H = np.ascontiguousarray(H)
+            Y = np.ascontiguousarray(Y, dtype=H.dtype)
+            s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
+            B, Nbs, K = H.shape
+            dt = H.dtype
+            hp, sp = H.ctypes.data, s2.ctypes.data
         R = Y.shape[2]
-        xhat = np.empty((B, K, R), dtype=H.dtype)
+        xhat = np.empty((B, K, R), dtype=dt)
         labels = np.empty((B, K, R), dtype=np.uint8)
         flags = np.empty((B,), dtype=np.uint32)
-        req = _Request(B, Nbs, K, R, 1 if H.dtype == np.complex64 else 0, qam, iters, L, sched,
-                       H.ctypes.data, Y.ctypes.data, s2.ctypes.data, xhat.ctypes.data, labels.ctypes.data,
-                       flags.ctypes.data)
+        req = _Request(B, Nbs, K, R, 1 if dt == np.complex64 else 0, qam, iters, L, sched,
+                       hp, Y.ctypes.data, sp, xhat.ctypes.data, labels.ctypes.data,
+                       flags.ctypes.data, channels or 0)
         t = ctypes.c_uint64()
         _check(lib().fpcg_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (H, Y, s2, xhat, labels, flags)

@@ -31,6 +31,15 @@ struct Req {
     fpcg_status status = FPCG_OK;
 };
 
+struct ChanSet {
+    int64_t B = 0;
+    int32_t Nbs = 0, K = 0, io_c64 = 0;
+    void* dH = nullptr;
+    double* dS = nullptr;
+    size_t bytes = 0;
+    int users = 0;          // queued or running requests reading it
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -47,13 +56,16 @@ struct Layout {
     size_t h, y, s2, x, lab, fl, total;
 };
 
+// slot buffer of a request; a request on a resident channel set has no H or
+// sigma^2 segment (zero-length, at the Y offset)
 Layout layout_of(const fpcg_request& r) {
     const size_t el = r.io_c64 ? 8 : 16;
+    const bool resident = r.channels != 0;
     Layout L;
     size_t o = 0;
-    L.h = o; o = align256(o + (size_t)r.B * r.Nbs * r.K * el);
+    L.h = o; o = resident ? o : align256(o + (size_t)r.B * r.Nbs * r.K * el);
     L.y = o; o = align256(o + (size_t)r.B * r.Nbs * r.R * el);
-    L.s2 = o; o = align256(o + (size_t)r.B * 8);
+    L.s2 = o; o = resident ? o : align256(o + (size_t)r.B * 8);
     L.x = o; o = align256(o + (size_t)r.B * r.K * r.R * el);
     L.lab = o; o = align256(o + (size_t)r.B * r.K * r.R);
     L.fl = o; o = align256(o + (size_t)r.B * 4);
@@ -70,7 +82,9 @@ struct fpcg_server {
     std::deque<Req*> queue;
     std::unordered_map<uint64_t, Req*> reqs;
     size_t held = 0;   // device bytes of all slot buffers
-    uint64_t next = 1;
+    std::unordered_map<uint64_t, ChanSet> chans;
+    size_t chan_bytes = 0;   // device bytes of the resident channel sets
+    uint64_t next = 1, next_chan = 1;
     std::mutex mu;
 };
 
@@ -92,6 +106,7 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
             if (rq->r.flags) std::memcpy(rq->r.flags, hb + L.fl, (size_t)rq->r.B * 4);
         }
         rq->state = 2;
+        if (rq->r.channels) s->chans[rq->r.channels].users--;
         sl.req = nullptr;
     }
     // admit in arrival order while a slot is free and the budget allows; the
@@ -107,7 +122,7 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
             for (Slot& sl : s->slots)
                 if (!sl.req) { pick = &sl; break; }
             if (!pick) break;                                      // every slot busy
-            if (s->held - pick->dcap + L.total > s->ctx->budget) {
+            if (s->held + s->chan_bytes - pick->dcap + L.total > s->ctx->budget) {
                 // release the buffers of the other idle slots, then try again
                 for (Slot& sl : s->slots) {
                     if (sl.req || &sl == pick || !sl.dbuf) continue;
@@ -116,7 +131,7 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
                     s->held -= sl.dcap;
                     sl.dbuf = nullptr; sl.hbuf = nullptr; sl.dcap = sl.hcap = 0;
                 }
-                if (s->held - pick->dcap + L.total > s->ctx->budget) break;   // wait for running requests
+                if (s->held + s->chan_bytes - pick->dcap + L.total > s->ctx->budget) break;   // wait for running requests
             }
             if (pick->dbuf) (void)hipFree(pick->dbuf);
             if (pick->hbuf) (void)hipHostFree(pick->hbuf);
@@ -129,6 +144,7 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
                 s->queue.pop_front();
                 rq->status = fail(FPCG_E_NOMEM, "device/pinned allocation of %zu bytes failed", L.total);
                 rq->state = 2;
+                if (rq->r.channels) s->chans[rq->r.channels].users--;
                 continue;
             }
             pick->dcap = pick->hcap = L.total;
@@ -141,16 +157,19 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
         const fpcg_request& r = rq->r;
         const size_t el = r.io_c64 ? 8 : 16;
         const size_t nh = (size_t)r.B * r.Nbs * r.K * el, ny = (size_t)r.B * r.Nbs * r.R * el;
-        std::memcpy(hb + L.h, r.H, nh);
+        const ChanSet* cs = r.channels ? &s->chans[r.channels] : nullptr;
+        if (!cs) std::memcpy(hb + L.h, r.H, nh);
         std::memcpy(hb + L.y, r.Y, ny);
-        std::memcpy(hb + L.s2, r.sigma2, (size_t)r.B * 8);
+        if (!cs) std::memcpy(hb + L.s2, r.sigma2, (size_t)r.B * 8);
         hipError_t e = hipMemcpyAsync(db, hb, L.x, hipMemcpyHostToDevice, sl.stream);
         fpcg_status st = FPCG_OK;
         if (e != hipSuccess) st = fail(FPCG_E_DEVICE, "H2D copy: %s", hipGetErrorString(e));
+        const void* dH = cs ? cs->dH : static_cast<const void*>(db + L.h);
+        const double* dS = cs ? cs->dS : reinterpret_cast<const double*>(db + L.s2);
         if (st == FPCG_OK)
-            st = launch_detect(s->ctx, sl.stream, rq->plan, r.B, r.Nbs, r.K, r.R, db + L.h, db + L.y, r.io_c64,
-                               reinterpret_cast<const double*>(db + L.s2), r.qam_order, r.iters, db + L.x,
-                               reinterpret_cast<uint8_t*>(db + L.lab), reinterpret_cast<uint32_t*>(db + L.fl));
+            st = launch_detect(s->ctx, sl.stream, rq->plan, r.B, r.Nbs, r.K, r.R, dH, db + L.y, r.io_c64, dS,
+                               r.qam_order, r.iters, db + L.x, reinterpret_cast<uint8_t*>(db + L.lab),
+                               reinterpret_cast<uint32_t*>(db + L.fl));
         if (st == FPCG_OK) {
             e = hipMemcpyAsync(hb + L.x, db + L.x, L.total - L.x, hipMemcpyDeviceToHost, sl.stream);
             if (e != hipSuccess) st = fail(FPCG_E_DEVICE, "D2H copy: %s", hipGetErrorString(e));
@@ -162,6 +181,7 @@ static fpcg_status retire_and_admit(fpcg_server* s) {
         if (st != FPCG_OK) {
             rq->status = st;
             rq->state = 2;
+            if (rq->r.channels) s->chans[rq->r.channels].users--;
             (void)hipStreamSynchronize(sl.stream);
             continue;
         }
@@ -200,11 +220,22 @@ fpcg_status fpcg_submit(fpcg_server* s, const fpcg_request* req, uint64_t* ticke
     Plan plan;
     fpcg_status st = check_args(req->B, req->Nbs, req->K, req->R, req->qam_order, req->iters, req->block_L, &req->sched, &plan);
     if (st != FPCG_OK) return st;
-    if (req->B > 0 && (!req->H || !req->Y || !req->sigma2 || !req->xhat || !req->labels))
+    const bool resident = req->channels != 0;
+    if (req->B > 0 && ((!resident && (!req->H || !req->sigma2)) || !req->Y || !req->xhat || !req->labels))
         return fail(FPCG_E_INVAL, "request buffers must be non-NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    if (resident) {
+        auto it = s->chans.find(req->channels);
+        if (it == s->chans.end())
+            return fail(FPCG_E_INVAL, "unknown channel set %llu", (unsigned long long)req->channels);
+        const ChanSet& c = it->second;
+        if (c.B != req->B || c.Nbs != req->Nbs || c.K != req->K || c.io_c64 != req->io_c64)
+            return fail(FPCG_E_INVAL, "request sizes do not match channel set %llu", (unsigned long long)req->channels);
+    }
     const size_t bytes = layout_of(*req).total;
-    if (bytes > s->ctx->budget) return fail(FPCG_E_NOMEM, "request needs %zu bytes, budget %zu", bytes, s->ctx->budget);
+    if (bytes + s->chan_bytes > s->ctx->budget)
+        return fail(FPCG_E_NOMEM, "request needs %zu bytes, budget %zu (%zu in channel sets)", bytes, s->ctx->budget,
+                    s->chan_bytes);
     if ((int)s->queue.size() >= s->cap) return fail(FPCG_E_BUSY, "queue full (%d)", s->cap);
     Req* rq = new Req();
     rq->ticket = s->next++;
@@ -213,6 +244,7 @@ fpcg_status fpcg_submit(fpcg_server* s, const fpcg_request* req, uint64_t* ticke
     rq->bytes = bytes;
     s->reqs[rq->ticket] = rq;
     s->queue.push_back(rq);
+    if (resident) s->chans[req->channels].users++;
     *ticket = rq->ticket;
     (void)hipSetDevice(s->ctx->device);
     return retire_and_admit(s);
@@ -254,6 +286,64 @@ fpcg_status fpcg_drain(fpcg_server* s) {
     }
 }
 
+fpcg_status fpcg_server_channels(fpcg_server* s, int64_t B, int32_t Nbs, int32_t K, int32_t io_c64, const void* H,
+                                 const double* sigma2, uint64_t* handle) {
+    clear_error();
+    if (!s || !handle) return fail(FPCG_E_INVAL, "NULL argument");
+    if (B < 1 || B > 0x7fffffffLL || Nbs < 1 || K < 1) return fail(FPCG_E_INVAL, "bad channel-set sizes");
+    if (!H || !sigma2) return fail(FPCG_E_INVAL, "H and sigma2 must be non-NULL");
+    const size_t nh = (size_t)B * Nbs * K * (io_c64 ? 8 : 16), ns = (size_t)B * 8;
+    std::lock_guard<std::mutex> lk(s->mu);
+    (void)hipSetDevice(s->ctx->device);
+    retire_and_admit(s);
+    if (s->held + s->chan_bytes + nh + ns > s->ctx->budget) {
+        // make room from idle slot buffers first
+        for (Slot& sl : s->slots) {
+            if (sl.req || !sl.dbuf) continue;
+            (void)hipFree(sl.dbuf);
+            (void)hipHostFree(sl.hbuf);
+            s->held -= sl.dcap;
+            sl.dbuf = nullptr; sl.hbuf = nullptr; sl.dcap = sl.hcap = 0;
+        }
+        if (s->held + s->chan_bytes + nh + ns > s->ctx->budget)
+            return fail(FPCG_E_NOMEM, "channel set of %zu bytes does not fit the budget", nh + ns);
+    }
+    ChanSet c;
+    c.B = B; c.Nbs = Nbs; c.K = K; c.io_c64 = io_c64 ? 1 : 0;
+    if (hipMalloc(&c.dH, nh) != hipSuccess || hipMalloc((void**)&c.dS, ns) != hipSuccess) {
+        if (c.dH) (void)hipFree(c.dH);
+        return fail(FPCG_E_NOMEM, "device allocation of %zu bytes failed", nh + ns);
+    }
+    if (hipMemcpy(c.dH, H, nh, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.dS, sigma2, ns, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(c.dH);
+        (void)hipFree(c.dS);
+        return fail(FPCG_E_DEVICE, "channel-set upload failed");
+    }
+    c.bytes = nh + ns;
+    const uint64_t h = s->next_chan++;
+    s->chans[h] = c;
+    s->chan_bytes += c.bytes;
+    *handle = h;
+    return FPCG_OK;
+}
+
+fpcg_status fpcg_server_release(fpcg_server* s, uint64_t handle) {
+    clear_error();
+    if (!s) return fail(FPCG_E_INVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->chans.find(handle);
+    if (it == s->chans.end()) return fail(FPCG_E_INVAL, "unknown channel set %llu", (unsigned long long)handle);
+    (void)hipSetDevice(s->ctx->device);
+    retire_and_admit(s);
+    if (it->second.users > 0) return fail(FPCG_E_BUSY, "channel set %llu is in use", (unsigned long long)handle);
+    (void)hipFree(it->second.dH);
+    (void)hipFree(it->second.dS);
+    s->chan_bytes -= it->second.bytes;
+    s->chans.erase(it);
+    return FPCG_OK;
+}
+
 fpcg_status fpcg_server_stats(fpcg_server* s, int32_t* in_flight, int32_t* queued, size_t* bytes_held) {
     clear_error();
     if (!s) return fail(FPCG_E_INVAL, "NULL server");
@@ -262,7 +352,7 @@ fpcg_status fpcg_server_stats(fpcg_server* s, int32_t* in_flight, int32_t* queue
     for (Slot& sl : s->slots) f += sl.req != nullptr;
     if (in_flight) *in_flight = f;
     if (queued) *queued = (int32_t)s->queue.size();
-    if (bytes_held) *bytes_held = s->held;
+    if (bytes_held) *bytes_held = s->held + s->chan_bytes;
     return FPCG_OK;
 }
 
@@ -274,6 +364,10 @@ void fpcg_server_destroy(fpcg_server* s) {
         if (sl.hbuf) (void)hipHostFree(sl.hbuf);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    for (auto& kv : s->chans) {
+        if (kv.second.dH) (void)hipFree(kv.second.dH);
+        if (kv.second.dS) (void)hipFree(kv.second.dS);
     }
     for (auto& kv : s->reqs) delete kv.second;
     delete s;

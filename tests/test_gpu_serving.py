@@ -112,3 +112,51 @@ def test_small_budget_admits_as_memory_frees():
     _say(f"  max in flight {max_flight}, max device bytes held {max_held}")
     _check_same(reqs, alone, served)
     assert max_held <= budget
+
+
+def test_resident_channel_sets_match_alone_bitwise():
+    """Channel sets uploaded once; requests carry only Y (several blocks of
+    received vectors per channel set) and match the direct launch bitwise;
+    idle sets are released."""
+    import paper_2504_09820_amd as fp
+
+    reqs = _requests(6, 13)
+    _say("case serving: 6 resident channel sets, 3 Y blocks each")
+    ctx = fp.Context(0)
+    srv = fp.Server(ctx, n_slots=4, queue_cap=64)
+    handles = [srv.channels(r["H"], r["s2"]) for r in reqs]
+    rng = np.random.default_rng(3)
+    jobs = []
+    for r, h in zip(reqs, handles):
+        for blk in range(3):
+            Yb = (r["Y"] * (1.0 + 0.25 * blk) + 0.01 * blk).astype(r["Y"].dtype)   # further received vectors
+            jobs.append((r, h, Yb))
+    order = rng.permutation(len(jobs))
+    tickets = {}
+    for i in order:
+        r, h, Yb = jobs[i]
+        tickets[i] = srv.submit(None, Yb, None, r["q"], r["iters"], r["L"], r["sched"], refresh_every=r["refresh"],
+                                variant=r["variant"], channels=h)
+    with pytest.raises(fp.FpcgError):
+        srv.release(987654)                       # not a channel set
+    out = {}
+    t0 = time.time()
+    while len(out) < len(jobs):
+        for i, t in tickets.items():
+            if i not in out:
+                res = srv.poll(t)
+                if res is not None:
+                    out[i] = res
+        assert time.time() - t0 < 60
+    for i, (r, h, Yb) in enumerate(jobs):
+        a = _alone(fp, dict(r, Y=Yb))
+        s = out[i]
+        assert np.array_equal(a[0].view(np.uint8), s[0].view(np.uint8)), f"job {i} x_hat differs"
+        assert np.array_equal(a[1], s[1]) and np.array_equal(a[2], s[2]), f"job {i} labels/flags differ"
+    _, _, held_before = srv.stats()
+    for h in handles:
+        srv.release(h)
+    _, _, held = srv.stats()
+    assert held < held_before
+    srv.close()
+    ctx.close()
