@@ -313,7 +313,7 @@ def main():
     if args.profile:
         cd = cands[0]
         it = args.iters or 11
-        wall, per = run(cd["sched"], it, cd["L"], variant, args.steps, args.warmup)
+        wall, per = run(cd["sched"], it, cd["L"], variant, args.steps, args.warmup, idle=2.0)
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # a plain copy of known size, to scale
         b = torch.empty_like(a)                                     # the HBM byte counters
         for _ in range(3):
