@@ -148,6 +148,8 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  * refresh / refinement, QAM slicer.  One fused kernel; nothing but inputs
  * and outputs touches device memory.
  *   B >= 0 channels (B = 0 is a no-op); Nbs >= 1; 1 <= K <= 128; R >= 1.
+ *   One channel's H, Y and x_hat must each stay below 2 GiB at complex128
+ *   size (16 Nbs max(K, R) < 2^31, 16 K R < 2^31), else FPCG_E_UNSUPPORTED.
  *   qam_order in {4, 16, 64, 256}; iters >= 0 (0 gives x_hat = 0).
  *   block_L = 0: Alg. 2 (no preconditioner); block_L in {4, 8, 16}: Alg. 3,
  *   block_L must divide K; each lane of the kernel owns whole Jacobi blocks,

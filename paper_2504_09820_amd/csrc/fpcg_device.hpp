@@ -31,6 +31,17 @@ __device__ __forceinline__ uint16_t f16_bits(float v) {
     _Float16 h = (_Float16)v;
     return __builtin_bit_cast(uint16_t, h);
 }
+// two fp32 -> two halves of one word (a in the low half), both rounded to
+// nearest even; one packed conversion (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f16x2_bits(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, f16x2));
+}
+__device__ __forceinline__ uint32_t bf16x2_bits(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
 // two fp32 -> two OCP e4m3 bytes (low 16 bits of the result)
 __device__ __forceinline__ uint32_t fp8x2_bits(float a, float b) {
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
@@ -125,7 +136,7 @@ template <> struct Op<BF16, 8> {
     __device__ static __forceinline__ frag pack(const float* v, float s) {
         frag r;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = (uint32_t)bf16_bits(v[2 * j] * s) | ((uint32_t)bf16_bits(v[2 * j + 1] * s) << 16);
+        for (int j = 0; j < 4; ++j) r[j] = bf16x2_bits(v[2 * j] * s, v[2 * j + 1] * s);
         return r;
     }
     __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
@@ -145,7 +156,7 @@ template <> struct Op<BF16, 4> {
     __device__ static __forceinline__ frag pack(const float* v, float s) {
         frag r;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) r[j] = (uint32_t)bf16_bits(v[2 * j] * s) | ((uint32_t)bf16_bits(v[2 * j + 1] * s) << 16);
+        for (int j = 0; j < 2; ++j) r[j] = bf16x2_bits(v[2 * j] * s, v[2 * j + 1] * s);
         return r;
     }
     __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
@@ -165,7 +176,7 @@ template <> struct Op<F16, 8> {
     __device__ static __forceinline__ frag pack(const float* v, float s) {
         frag r;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = (uint32_t)f16_bits(v[2 * j] * s) | ((uint32_t)f16_bits(v[2 * j + 1] * s) << 16);
+        for (int j = 0; j < 4; ++j) r[j] = f16x2_bits(v[2 * j] * s, v[2 * j + 1] * s);
         return r;
     }
     __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
@@ -185,7 +196,7 @@ template <> struct Op<F16, 4> {
     __device__ static __forceinline__ frag pack(const float* v, float s) {
         frag r;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) r[j] = (uint32_t)f16_bits(v[2 * j] * s) | ((uint32_t)f16_bits(v[2 * j + 1] * s) << 16);
+        for (int j = 0; j < 2; ++j) r[j] = f16x2_bits(v[2 * j] * s, v[2 * j + 1] * s);
         return r;
     }
     __device__ static __forceinline__ frag neg(frag a) { return a ^ 0x80008000u; }
@@ -277,10 +288,8 @@ __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(
 template <typename T> __device__ __forceinline__ int slice_axis(T v, T nu, T mm, int m) {
     T t = add_rn(mul_rn(v, nu), mm);
     T j = floor(t * T(0.5));
-    if (!__builtin_isfinite(j)) return 0;
-    if (j < T(0)) return 0;
-    if (j > T(m - 1)) return m - 1;
-    return (int)j;
+    const T jc = fmin(fmax(j, T(0)), T(m - 1));      // index clamped to [0, m-1]
+    return __builtin_isfinite(j) ? (int)jc : 0;       // a non-finite estimate maps to index 0
 }
 
 template <typename T> __device__ __forceinline__ uint8_t slice_label(T re, T im, T nu, T mm, int m, int bits) {
@@ -315,6 +324,11 @@ template <> struct CxB<float> {
         re = (T)__uint_as_float(lo);
         im = (T)__uint_as_float(hi);
     }
+    // store re + i im as complex64 (values outside the range are dropped)
+    template <typename T> __device__ static __forceinline__ void store(const Buf& b, uint32_t off, T re, T im) {
+        const u32x2v v = {__float_as_uint((float)re), __float_as_uint((float)im)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, b.r, off, 0, 0);
+    }
 };
 template <> struct CxB<double> {
     static constexpr uint32_t bytes = 16;
@@ -325,7 +339,17 @@ template <> struct CxB<double> {
         re = (T)__longlong_as_double((long long)a);
         im = (T)__longlong_as_double((long long)c);
     }
+    // store re + i im as complex128 (values outside the range are dropped)
+    template <typename T> __device__ static __forceinline__ void store(const Buf& b, uint32_t off, T re, T im) {
+        const uint64_t a = (uint64_t)__double_as_longlong((double)re), c = (uint64_t)__double_as_longlong((double)im);
+        const u32x4v v = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)c, (uint32_t)(c >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, 0);
+    }
 };
+// one byte (values outside the range are dropped)
+__device__ __forceinline__ void store_u8(const Buf& b, uint32_t off, uint8_t v) {
+    __builtin_amdgcn_raw_buffer_store_b8(v, b.r, off, 0, 0);
+}
 
 // complex element loads/stores for complex64 (float) or complex128 (double) I/O
 template <typename IOT> struct Cx;

@@ -53,6 +53,39 @@ struct FusedParams {
     int32_t m, bits;
 };
 
+// Lanes of the symmetric block-Jacobi transform.  Pass 1 (rows) needs rows
+// m < (b+1) L of block b, pass 2 (columns) columns n >= b L: (b+1) L and
+// (NB-b) L items.  A block gets ceil(items / N) lanes for the smallest N
+// (items per lane) whose lane total fits the workgroup.
+template <int KP, int LB, int NT> struct SplitPlan {
+    static constexpr int NB = LB > 0 ? KP / LB : 1;
+    static constexpr int items(int b, bool rows) { return (rows ? b + 1 : NB - b) * LB; }
+    static constexpr int lanes(int b, bool rows, int n) { return (items(b, rows) + n - 1) / n; }
+    static constexpr int total(bool rows, int n) {
+        int t = 0;
+        for (int b = 0; b < NB; ++b) t += lanes(b, rows, n);
+        return t;
+    }
+    static constexpr int per_lane(bool rows) {
+        int n = 1;
+        while (total(rows, n) > NT) ++n;
+        return n;
+    }
+    static constexpr int NIR = LB > 0 ? per_lane(true) : 1, NIC = LB > 0 ? per_lane(false) : 1;
+    // this lane's block b, its rank r among the block's nl lanes, and whether it serves at all
+    __device__ static __forceinline__ void assign(int tid, bool rows, int& b, int& r, int& nl, bool& serves) {
+        const int n = rows ? NIR : NIC;
+        int first = 0;
+        b = 0; r = 0; nl = 1; serves = false;
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            const int c = lanes(bb, rows, n);
+            if (tid >= first && tid < first + c) { b = bb; r = tid - first; nl = c; serves = true; }
+            first += c;
+        }
+    }
+};
+
 template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr int KP = KP_, NW = NW_, FMT = FMT_, LB = LB_;
     static constexpr bool LOWP = (FMT != F64 && FMT != F32);
@@ -204,6 +237,16 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     constexpr uint32_t ES = CxB<IOT>::bytes;
     const Buf bH(static_cast<const char*>(P.H) + hoff * ES, (uint32_t)Nbs * K * ES);   // this channel's H
     const Buf bY(static_cast<const char*>(P.Y) + yoff * ES, (uint32_t)Nbs * R * ES);   // this channel's Y
+    // this channel's outputs (x_hat, labels) and the per-lane part of their
+    // offsets: an invalid received-vector column stores nothing, and padded
+    // rows fall past the end of the ranges
+    auto store_out = [&](int c, auto xr, auto xi, uint8_t label) {
+        const Buf bXo(static_cast<char*>(P.xhat) + (int64_t)ch * K * R * ES, (uint32_t)K * R * ES);
+        const Buf bLo(P.labels + (int64_t)ch * K * R, (uint32_t)K * R);
+        const uint32_t o = (uint32_t)c * R;
+        CxB<IOT>::store(bXo, (colv ? (uint32_t)col * ES : OOB) + o * ES, xr, xi);
+        store_u8(bLo, (colv ? (uint32_t)col : OOB) + o, label);
+    };
     auto hofs = [&](int a, int k) -> uint32_t { return (a < Nbs && k < K) ? ((uint32_t)a * K + k) * ES : OOB; };
     auto yofs = [&](int a) -> uint32_t { return (a < Nbs && colv) ? ((uint32_t)a * R + col) * ES : OOB; };
     const double s2 = P.sigma2[ch];
@@ -287,17 +330,26 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         for (int s = 0; s < MFPW; ++s) { gBr[s] = acc_t{0, 0, 0, 0}; gBi[s] = acc_t{0, 0, 0, 0}; }
 
         constexpr int NSUB = C::NSUB, NLD = KPLG * NSUB;
+        // per-lane part of the load offsets, fixed for the whole loop: a padded
+        // user column (k >= K) or received-vector column (col >= R) starts at
+        // OOB, so every load of it reads zero; antennas a >= Nbs lie past the
+        // end of the channel's range and read zero as well
+        uint32_t hl[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) hl[f] = (16 * f + n < K) ? (uint32_t)(16 * f + n) * ES : OOB;
+        const uint32_t yl = colv ? (uint32_t)col * ES : OOB;
+        const uint32_t hrow = (uint32_t)K * ES, yrow = (uint32_t)R * ES;
         for (int a0 = 0; a0 < Nbs; a0 += KBG) {
-            // range-checked loads (padding reads zero): all loads of the block in
-            // flight together; lane (g, n) takes antennas a0 + g NLD + j, j < NLD,
-            // the same for H and Y, so every MFMA contracts matching antennas
+            // range-checked loads: all loads of the block in flight together;
+            // lane (g, n) takes antennas a0 + g NLD + j, j < NLD, the same for H
+            // and Y, so every MFMA contracts matching antennas
             Wt hr[F][NLD], hi[F][NLD], yr[NLD], yi[NLD];
+            const uint32_t ab = (uint32_t)(a0 + g * NLD);
 #pragma unroll
             for (int j = 0; j < NLD; ++j) {
-                const int a = a0 + g * NLD + j;
 #pragma unroll
-                for (int f = 0; f < F; ++f) CxB<IOT>::load(bH, hofs(a, 16 * f + n), hr[f][j], hi[f][j]);
-                CxB<IOT>::load(bY, yofs(a), yr[j], yi[j]);
+                for (int f = 0; f < F; ++f) CxB<IOT>::load(bH, hl[f] + (ab + j) * hrow, hr[f][j], hi[f][j]);
+                CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
             }
 #pragma unroll
             for (int u = 0; u < NSUB; ++u) {
@@ -341,6 +393,9 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         const Wt invH = (Wt)ldexpf(1.f, -eH), invY = (Wt)ldexpf(1.f, -eY);
         const Wt s2w = (Wt)s2;
         bool bad = false;
+        // non-finite check of many values at one FMA each: v * 0 is NaN exactly
+        // when v is infinite or NaN, and a NaN stays in the sum
+        Wt nfa = 0;
         // the u_W value of one Gram element (sigma^2 on the diagonal, padding diagonal 1)
         auto gram_at = [&](int s, int jj, int row, int cc, Wt& ar, Wt& ai) {
             ar = (Wt)gAr[s][jj];
@@ -433,7 +488,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                             ai = 0;
                             ar = (row < K) ? ar + s2w : (Wt)1;
                         }
-                        bad |= !__builtin_isfinite(ar) || !__builtin_isfinite(ai);
+                        nfa = fma(ar, (Wt)0, fma(ai, (Wt)0, nfa));
                         sAr[row * LDA + cc] = ar;
                         sAi[row * LDA + cc] = ai;
                         if (f1 != f2) {
@@ -455,7 +510,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                     const int row = 16 * f + OG::crow(g, jj);
                     Wt br = (Wt)gBr[s][jj], bi = (Wt)gBi[s][jj];
                     if constexpr (FMT == F8) { br = br * invH * invY; bi = bi * invH * invY; }
-                    bad |= !__builtin_isfinite(br) || !__builtin_isfinite(bi);
+                    nfa = fma(br, (Wt)0, fma(bi, (Wt)0, nfa));
                     bcr[s][jj] = br;
                     bci[s][jj] = bi;
                     if (!compact) {
@@ -465,7 +520,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 }
             }
         }
-        if (bad) myflag |= FLAG_NONFINITE;
+        if (bad || !__builtin_isfinite(nfa)) myflag |= FLAG_NONFINITE;
     }
     }
     if constexpr (MODE == MODE_GRAM) {
@@ -646,27 +701,34 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             //   W = A T^H:   W[m][bL + c] = sum_{j <= c} A[m][bL + j] conj(T[bL + c][bL + j])
             //   A = T W:     A[bL + r][n] = sum_{j <= r} T[bL + r][bL + j] W[bL + j][n]
             // Items (row m or column n, block b) are independent and update only
-            // their own L-segment.  Each lane keeps one block b of T in registers
-            // and takes the items of that block (rows, then columns, strided);
-            // loads are unconditional, stores guarded to what the upper triangle needs.
-            constexpr int NB = KP / LB, RPL = NT / NB, NIT = KP / RPL;
-            static_assert(NT % NB == 0 && KP % RPL == 0, "lanes split evenly over the blocks");
-            const int b = tid % NB, q = tid / NB;
-            // the block of T in registers for L <= 4; for larger blocks it is read
-            // from LDS next to each item's loads (register budget)
+            // their own L-segment.  Only the items the upper triangle needs are
+            // computed: rows m < (b+1) L of block b in the first pass, columns
+            // n >= b L in the second.  Each lane serves one block; a block gets
+            // lanes in proportion to its items (SplitPlan), so every lane has at
+            // most NIR (NIC) items.  The lane keeps its block of T in registers
+            // (L <= 4) or reads it from LDS next to each item's loads.
+            using SPl = SplitPlan<KP, LB, NT>;
             constexpr bool TREG = LB <= 4;
             Wt Tr_[TREG ? LB : 1][TREG ? LB : 1], Ti_[TREG ? LB : 1][TREG ? LB : 1];
-            if constexpr (TREG) {
+            int b = 0, r0 = 0, nl = 1;
+            bool sv = false;
+            auto load_T = [&]() {
+                if constexpr (TREG) {
 #pragma unroll
-                for (int r = 0; r < LB; ++r)
+                    for (int r = 0; r < LB; ++r)
 #pragma unroll
-                    for (int j = 0; j <= r; ++j) { Tr_[r][j] = sMr[(b * LB + r) * LB + j]; Ti_[r][j] = sMi[(b * LB + r) * LB + j]; }
-            }
+                        for (int j = 0; j <= r; ++j) { Tr_[r][j] = sMr[(b * LB + r) * LB + j]; Ti_[r][j] = sMi[(b * LB + r) * LB + j]; }
+                }
+            };
             auto Tr = [&](int r, int j) -> Wt { if constexpr (TREG) return Tr_[r][j]; else return sMr[(b * LB + r) * LB + j]; };
             auto Ti = [&](int r, int j) -> Wt { if constexpr (TREG) return Ti_[r][j]; else return sMi[(b * LB + r) * LB + j]; };
+            SPl::assign(tid, true, b, r0, nl, sv);
+            load_T();
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const int m = q + it * RPL;
+            for (int it = 0; it < SPl::NIR; ++it) {
+                const int mi = r0 + it * nl;
+                const bool need = sv && mi < (b + 1) * LB;
+                const int m = need ? mi : 0;                // loads stay in the matrix
                 Wt a_r[LB], a_i[LB];
 #pragma unroll
                 for (int j = 0; j < LB; ++j) { a_r[j] = sAr[m * LDA + b * LB + j]; a_i[j] = sAi[m * LDA + b * LB + j]; }
@@ -684,15 +746,19 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                     w_r[c] = wr;
                     w_i[c] = wi;
                 }
-                if (m / LB <= b) {                          // rows the upper triangle needs
+                if (need) {
 #pragma unroll
                     for (int c = 0; c < LB; ++c) { sAr[m * LDA + b * LB + c] = w_r[c]; sAi[m * LDA + b * LB + c] = w_i[c]; }
                 }
             }
             bsync();
+            SPl::assign(tid, false, b, r0, nl, sv);
+            load_T();
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const int nn = q + it * RPL;
+            for (int it = 0; it < SPl::NIC; ++it) {
+                const int ni = b * LB + r0 + it * nl;
+                const bool need = sv && ni < KP;
+                const int nn = need ? ni : 0;
                 Wt w_r[LB], w_i[LB];
 #pragma unroll
                 for (int j = 0; j < LB; ++j) { w_r[j] = sAr[(b * LB + j) * LDA + nn]; w_i[j] = sAi[(b * LB + j) * LDA + nn]; }
@@ -710,7 +776,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                     v_r[r] = vr;
                     v_i[r] = vi;
                 }
-                if (b * LB <= nn) {                         // blocks of rows that reach the upper triangle
+                if (need) {
 #pragma unroll
                     for (int r = 0; r < LB; ++r) { sAr[(b * LB + r) * LDA + nn] = v_r[r]; sAi[(b * LB + r) * LDA + nn] = v_i[r]; }
                 }
@@ -1081,13 +1147,21 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         }
 
         // ------------------------------------------------ 3. (P)CG
-        Wt rr[SH], ri[SH], pr[SH], pi[SH];
+        // x of this pass: in registers where it fits beside the other vectors
+        // (stored to LDS only for an FP64 refresh), else accumulated in LDS
+        // (FP64: measured no faster in registers, and it spills more)
+        constexpr bool xreg = SH * sizeof(Wt) <= 32 && FMT != F64;
+        Wt rr[SH], ri[SH], pr[SH], pi[SH], xr_[SH], xi_[SH];
         {
             Wt wr[SH], wi[SH];
 #pragma unroll
             for (int e = 0; e < SH; ++e) {
-                sXr[e * NT + tid] = 0;
-                sXi[e * NT + tid] = 0;
+                xr_[e] = 0;
+                xi_[e] = 0;
+                if constexpr (!xreg) {
+                    sXr[e * NT + tid] = 0;
+                    sXi[e * NT + tid] = 0;
+                }
                 rr[e] = sBr[(base_c + e) * 16 + n];
                 ri[e] = sBi[(base_c + e) * 16 + n];
             }
@@ -1190,17 +1264,29 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             live = ok;
             if (live) {
                 const Wt alpha = rho_prev / ph;
+                if constexpr (!xreg) {
+#pragma unroll
+                    for (int e = 0; e < SH; ++e) { xr_[e] = sXr[e * NT + tid]; xi_[e] = sXi[e * NT + tid]; }
+                }
 #pragma unroll
                 for (int e = 0; e < SH; ++e) {
-                    sXr[e * NT + tid] = fma(alpha, pr[e], sXr[e * NT + tid]);
-                    sXi[e * NT + tid] = fma(alpha, pi[e], sXi[e * NT + tid]);
+                    xr_[e] = fma(alpha, pr[e], xr_[e]);
+                    xi_[e] = fma(alpha, pi[e], xi_[e]);
                     rr[e] = fma(-alpha, wr[e], rr[e]);
                     ri[e] = fma(-alpha, wi[e], ri[e]);
+                }
+                if constexpr (!xreg) {
+#pragma unroll
+                    for (int e = 0; e < SH; ++e) { sXr[e * NT + tid] = xr_[e]; sXi[e * NT + tid] = xi_[e]; }
                 }
             }
             // ---- FP64 residual refresh on the stored Gram (A, or T A T^H)
             // (not built for AROW: no u_W Gram is kept; refused on the host)
             if (!C::AROW && P.refresh_every > 0 && it % P.refresh_every == 0 && it < P.iters) {
+                if constexpr (xreg) {
+#pragma unroll
+                    for (int e = 0; e < SH; ++e) { sXr[e * NT + tid] = xr_[e]; sXi[e * NT + tid] = xi_[e]; }
+                }
                 if constexpr (NW > 1) __syncthreads();   // x of every wave visible
                 f64x4 Rr[NF], Ri[NF];
 #pragma unroll
@@ -1237,6 +1323,11 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                         }
                 }
                 if constexpr (NW > 1) __syncthreads();   // before x changes again
+                if constexpr (xreg) {
+                    // reloaded, so that x is not held in registers across the refresh
+#pragma unroll
+                    for (int e = 0; e < SH; ++e) { xr_[e] = sXr[e * NT + tid]; xi_[e] = sXi[e * NT + tid]; }
+                }
             }
             // ---- z = M r (left form) or r, rho_i, beta, p
             Wt zr[SH], zi[SH];
@@ -1265,28 +1356,29 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         if (pass == 0) {
             Wt xo_r[SH], xo_i[SH];
 #pragma unroll
-            for (int e = 0; e < SH; ++e) { xo_r[e] = sXr[e * NT + tid]; xo_i[e] = sXi[e * NT + tid]; }
+            for (int e = 0; e < SH; ++e) {
+                xo_r[e] = xreg ? xr_[e] : sXr[e * NT + tid];
+                xo_i[e] = xreg ? xi_[e] : sXi[e * NT + tid];
+            }
             if constexpr (split) apply_TH(xo_r, xo_i);  // x = T^H x_bar  (u_W)
             if (REF && P.refine_steps > 0) {
 #pragma unroll
                 for (int e = 0; e < SH; ++e) { sX64r[e * NT + tid] = (double)xo_r[e]; sX64i[e * NT + tid] = (double)xo_i[e]; }
-            } else if (colv) {
-                // ---- 5. slicer + stores (no refinement)
+            } else {
+                // ---- 5. slicer + stores (no refinement); padded rows and
+                // columns fall outside the output ranges and are dropped
                 const Wt nu = (Wt)P.nu, mm = (Wt)P.m;
 #pragma unroll
-                for (int e = 0; e < SH; ++e) {
-                    const int c = base_c + e;
-                    if (c < K) {
-                        const int64_t o = (ch * K + c) * (int64_t)R + col;
-                        Cx<IOT>::store(P.xhat, o, xo_r[e], xo_i[e]);
-                        P.labels[o] = slice_label<Wt>(xo_r[e], xo_i[e], nu, mm, P.m, P.bits);
-                    }
-                }
+                for (int e = 0; e < SH; ++e)
+                    store_out(base_c + e, xo_r[e], xo_i[e], slice_label<Wt>(xo_r[e], xo_i[e], nu, mm, P.m, P.bits));
             }
         } else {
             double dr[SH], di[SH];
 #pragma unroll
-            for (int e = 0; e < SH; ++e) { dr[e] = (double)sXr[e * NT + tid]; di[e] = (double)sXi[e * NT + tid]; }
+            for (int e = 0; e < SH; ++e) {
+                dr[e] = (double)(xreg ? xr_[e] : sXr[e * NT + tid]);
+                di[e] = (double)(xreg ? xi_[e] : sXi[e * NT + tid]);
+            }
             if constexpr (split) apply_TH(dr, di);      // d = T^H d_bar  (FP64 arithmetic)
             const double us = ldexp(1.0, es);          // x += d / sc, exact scaling
 #pragma unroll
@@ -1299,17 +1391,12 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     }
 
     // ------------------------------------------------------------ 5. slicer + stores (refined, FP64)
-    if (REF && colv && P.refine_steps > 0) {
+    if (REF && P.refine_steps > 0) {
         const double nu = P.nu, mm = (double)P.m;
 #pragma unroll
         for (int e = 0; e < SH; ++e) {
-            const int c = base_c + e;
-            if (c < K) {
-                const int64_t o = (ch * K + c) * (int64_t)R + col;
-                const double xr = sX64r[e * NT + tid], xi = sX64i[e * NT + tid];
-                Cx<IOT>::store(P.xhat, o, xr, xi);
-                P.labels[o] = slice_label<double>(xr, xi, nu, mm, P.m, P.bits);
-            }
+            const double xr = sX64r[e * NT + tid], xi = sX64i[e * NT + tid];
+            store_out(base_c + e, xr, xi, slice_label<double>(xr, xi, nu, mm, P.m, P.bits));
         }
     }
     const bool one_block = P.R <= 16;                  // the only workgroup / item of this channel

@@ -98,6 +98,10 @@ fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
     if (s->work != want_work || s->ip != want_work)
         return fail(FPCG_E_UNSUPPORTED, "work and ip must be %s for mv_op %d", want_work == FPCG_F64 ? "F64" : "F32", s->mv_op);
     if (K > 128) return fail(FPCG_E_UNSUPPORTED, "K=%d > 128 is not built", K);
+    // per-channel byte ranges of H, Y and x_hat (complex128 at most) are 32-bit
+    // buffer ranges below the out-of-range offset 2^31
+    if ((int64_t)Nbs * std::max(K, R) * 16 >= (1LL << 31) || (int64_t)K * R * 16 >= (1LL << 31))
+        return fail(FPCG_E_UNSUPPORTED, "Nbs=%d, K=%d, R=%d: one channel's data exceeds 2 GiB", Nbs, K, R);
     if (L != 0 && L != 4 && L != 8 && L != 16) return fail(FPCG_E_UNSUPPORTED, "block_L=%d not built (0, 4, 8, 16)", L);
     // map the public format enum to the kernel enum (identical values)
     const int fmt = s->mv_op;

@@ -52,6 +52,7 @@ def test_check_accepts_built_configurations(fp):
     assert fp.check(0, 1, 1, 1, 4, 0, 0, None) == 0          # empty batch, FP64 default
     assert fp.check(3, 1, 1, 1, 4, 1, 0, fp.schedule("fp64")) == 0
     assert fp.check(3, 50, 20, 17, 16, 5, 4, fp.schedule("fp32", refine_steps=2)) == 0
+    assert fp.check(1, 2**20 - 1, 128, 1, 16, 8, 0, fp.schedule("fp16")) == 0   # just below 2 GiB
 
 
 @pytest.mark.parametrize("args,code", [
@@ -69,6 +70,8 @@ def test_check_accepts_built_configurations(fp):
     ((10, 64, 32, 1, 16, 8, 16), -4),   # L = 16 not built for fp32 operands
     ((10, 64, 32, 1, 16, 8, 32), -4),   # L = 32 not built
     ((10, 64, 16, 1, 16, 8, 2), -4),    # L = 2 not built
+    ((10, 2**24, 8, 1, 16, 8, 0), -4),     # one channel's H reaches 2 GiB (complex128)
+    ((10, 64, 8, 2**21, 16, 8, 0), -4),    # one channel's Y reaches 2 GiB
 ])
 def test_check_rejects(fp, args, code):
     assert fp.check(*args, fp.schedule("fp32")) == code
