@@ -164,6 +164,11 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     __host__ __device__ static constexpr size_t lds_general(bool split, bool refine, int refresh_every) {
         return off_X(split) + (x_in_gram(refresh_every) ? 0 : sz_X) + (refine ? sz_X64 : 0);
     }
+    // the outputs of one channel with up to 16 received vectors (x_hat with
+    // es bytes per element, then its labels) fit the Gram's slot for staging
+    __host__ __device__ static constexpr bool stage_fits(size_t es) {
+        return (size_t)KP * 16 * es + 16 + (size_t)KP * 16 <= 2 * sz_Aplane;
+    }
     // bytes of a one-workgroup-per-channel launch
     __host__ __device__ static constexpr size_t lds(bool split, bool refine, int refresh_every) {
         return compact(refine, refresh_every) ? off_X(split) - sz_B : lds_general(split, refine, refresh_every);
@@ -240,12 +245,50 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     // this channel's outputs (x_hat, labels) and the per-lane part of their
     // offsets: an invalid received-vector column stores nothing, and padded
     // rows fall past the end of the ranges
+    // Outputs.  With one block of received vectors per channel (R <= 16) and
+    // a whole-channel workgroup, x_hat and the labels are staged in the
+    // Gram's LDS slot (dead once the last solve is done) and written as
+    // 16-byte chunks of the channel's contiguous output blocks, x_hat
+    // non-temporal: whole lines instead of one 14-element row segment per
+    // lane group (measured at c2: less write traffic and shorter launches).
+    // Otherwise each element goes straight out through the channel's buffer
+    // ranges; padded rows and columns fall outside them and are dropped.
+    const bool stage = C::stage_fits(ES) && MODE == MODE_FULL && R <= 16;
+    unsigned char* so_x = sbuf + C::off_Ar;
+    unsigned char* so_l = so_x + (((size_t)K * R * ES + 15) & ~(size_t)15);
+    auto out_begin = [&]() { if (stage) bsync(); };   // every wave is done with the Gram's slot
     auto store_out = [&](int c, auto xr, auto xi, uint8_t label) {
+        if (stage) {
+            if (colv && c < K) {
+                const int o = c * R + col;
+                IOT* px = reinterpret_cast<IOT*>(so_x + (size_t)o * ES);
+                px[0] = (IOT)xr;
+                px[1] = (IOT)xi;
+                so_l[o] = label;
+            }
+        } else {
+            const Buf bXo(static_cast<char*>(P.xhat) + (int64_t)ch * K * R * ES, (uint32_t)K * R * ES);
+            const Buf bLo(P.labels + (int64_t)ch * K * R, (uint32_t)K * R);
+            const uint32_t o = (uint32_t)c * R;
+            CxB<IOT>::store(bXo, (colv ? (uint32_t)col * ES : OOB) + o * ES, xr, xi);
+            store_u8(bLo, (colv ? (uint32_t)col : OOB) + o, label);
+        }
+    };
+    auto out_end = [&]() {
+        if (!stage) return;
+        bsync();
         const Buf bXo(static_cast<char*>(P.xhat) + (int64_t)ch * K * R * ES, (uint32_t)K * R * ES);
         const Buf bLo(P.labels + (int64_t)ch * K * R, (uint32_t)K * R);
-        const uint32_t o = (uint32_t)c * R;
-        CxB<IOT>::store(bXo, (colv ? (uint32_t)col * ES : OOB) + o * ES, xr, xi);
-        store_u8(bLo, (colv ? (uint32_t)col : OOB) + o, label);
+        const uint32_t nx = (uint32_t)K * R * ES, nl = (uint32_t)K * R;
+        for (uint32_t i = tid * 16u; i + 16u <= nx; i += NT * 16u)
+            store_b128<CP_STREAM>(bXo, i, *reinterpret_cast<const u32x4v*>(so_x + i));
+        if ((nx & 15u) && tid == 0) {                   // an odd element count leaves 8 bytes
+            const uint32_t i = nx & ~15u;
+            store_b64<CP_STREAM>(bXo, i, *reinterpret_cast<const u32x2v*>(so_x + i));
+        }
+        for (uint32_t i = tid * 16u; i + 16u <= nl; i += NT * 16u)
+            store_b128<0>(bLo, i, *reinterpret_cast<const u32x4v*>(so_l + i));
+        for (uint32_t i = (nl & ~15u) + tid; i < nl; i += NT) store_u8(bLo, i, so_l[i]);
     };
     auto hofs = [&](int a, int k) -> uint32_t { return (a < Nbs && k < K) ? ((uint32_t)a * K + k) * ES : OOB; };
     auto yofs = [&](int a) -> uint32_t { return (a < Nbs && colv) ? ((uint32_t)a * R + col) * ES : OOB; };
@@ -1012,6 +1055,13 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         }
     };
 
+    // flags raised so far, made wave-uniform (scalar registers) so that no
+    // vector register holds them through the solve
+    uint32_t wflag = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (__ballot((myflag >> b) & 1u) != 0) wflag |= 1u << b;
+    myflag = 0u;
     const int passes = REF ? 1 + P.refine_steps : 1;   // REF: built with FP64 refinement
     int es = 0;                                       // exponent of the current pass's residual scale
     for (int pass = 0; pass < passes; ++pass) {
@@ -1368,9 +1418,11 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 // ---- 5. slicer + stores (no refinement); padded rows and
                 // columns fall outside the output ranges and are dropped
                 const Wt nu = (Wt)P.nu, mm = (Wt)P.m;
+                out_begin();
 #pragma unroll
                 for (int e = 0; e < SH; ++e)
                     store_out(base_c + e, xo_r[e], xo_i[e], slice_label<Wt>(xo_r[e], xo_i[e], nu, mm, P.m, P.bits));
+                out_end();
             }
         } else {
             double dr[SH], di[SH];
@@ -1393,12 +1445,15 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     // ------------------------------------------------------------ 5. slicer + stores (refined, FP64)
     if (REF && P.refine_steps > 0) {
         const double nu = P.nu, mm = (double)P.m;
+        out_begin();
 #pragma unroll
         for (int e = 0; e < SH; ++e) {
             const double xr = sX64r[e * NT + tid], xi = sX64i[e * NT + tid];
             store_out(base_c + e, xr, xi, slice_label<double>(xr, xi, nu, mm, P.m, P.bits));
         }
+        out_end();
     }
+    myflag |= wflag;
     const bool one_block = P.R <= 16;                  // the only workgroup / item of this channel
     if constexpr (MODE == MODE_FULL) {
         if (myflag) atomicOr(&sFlag, myflag);
