@@ -306,10 +306,12 @@ template <typename T> __device__ __forceinline__ uint8_t slice_label(T re, T im,
 typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
 constexpr uint32_t OOB = 0x80000000u;   // any offset >= the range reads 0
-// cache policy of the complex loads and stores: non-temporal (streaming).
-// H, Y and x_hat are touched once per launch; measured at c2 the launch ran
-// 155 us instead of 167 us from an idle board (byte stores of the labels keep
-// the default policy: as non-temporal stores they measured slower)
+// Cache policy of a buffer access: non-temporal (streaming) for data touched
+// once whose 128-byte lines are consumed whole by one access (H rows of a
+// multiple of 128 bytes, the staged x_hat chunks); the default policy where
+// neighbouring rows share lines (Y rows of R = 14 complex64 values are 112
+// bytes: non-temporal loads of them fetched shared lines twice and measured
+// 30 us slower at c2).
 constexpr int CP_STREAM = 2;
 
 struct Buf {
@@ -323,8 +325,8 @@ template <typename IOT> struct CxB;
 // directly to an ext-vector element reads the vector's first element)
 template <> struct CxB<float> {
     static constexpr uint32_t bytes = 8;
-    template <typename T> __device__ static __forceinline__ void load(const Buf& b, uint32_t off, T& re, T& im) {
-        const u32x2v v = __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, CP_STREAM);
+    template <int CP = 0, typename T> __device__ static __forceinline__ void load(const Buf& b, uint32_t off, T& re, T& im) {
+        const u32x2v v = __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, CP);
         const uint32_t lo = v[0], hi = v[1];
         re = (T)__uint_as_float(lo);
         im = (T)__uint_as_float(hi);
@@ -332,13 +334,13 @@ template <> struct CxB<float> {
     // store re + i im as complex64 (values outside the range are dropped)
     template <typename T> __device__ static __forceinline__ void store(const Buf& b, uint32_t off, T re, T im) {
         const u32x2v v = {__float_as_uint((float)re), __float_as_uint((float)im)};
-        __builtin_amdgcn_raw_buffer_store_b64(v, b.r, off, 0, CP_STREAM);
+        __builtin_amdgcn_raw_buffer_store_b64(v, b.r, off, 0, 0);
     }
 };
 template <> struct CxB<double> {
     static constexpr uint32_t bytes = 16;
-    template <typename T> __device__ static __forceinline__ void load(const Buf& b, uint32_t off, T& re, T& im) {
-        const u32x4v v = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, CP_STREAM);
+    template <int CP = 0, typename T> __device__ static __forceinline__ void load(const Buf& b, uint32_t off, T& re, T& im) {
+        const u32x4v v = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, CP);
         const uint64_t a = ((uint64_t)(uint32_t)v[1] << 32) | (uint32_t)v[0];
         const uint64_t c = ((uint64_t)(uint32_t)v[3] << 32) | (uint32_t)v[2];
         re = (T)__longlong_as_double((long long)a);
@@ -348,7 +350,7 @@ template <> struct CxB<double> {
     template <typename T> __device__ static __forceinline__ void store(const Buf& b, uint32_t off, T re, T im) {
         const uint64_t a = (uint64_t)__double_as_longlong((double)re), c = (uint64_t)__double_as_longlong((double)im);
         const u32x4v v = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)c, (uint32_t)(c >> 32)};
-        __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, CP_STREAM);
+        __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, 0);
     }
 };
 // 16 and 8 bytes with cache policy CP (values outside the range are dropped)

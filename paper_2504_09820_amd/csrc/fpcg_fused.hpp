@@ -382,55 +382,61 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         for (int f = 0; f < F; ++f) hl[f] = (16 * f + n < K) ? (uint32_t)(16 * f + n) * ES : OOB;
         const uint32_t yl = colv ? (uint32_t)col * ES : OOB;
         const uint32_t hrow = (uint32_t)K * ES, yrow = (uint32_t)R * ES;
-        for (int a0 = 0; a0 < Nbs; a0 += KBG) {
-            // range-checked loads: all loads of the block in flight together;
-            // lane (g, n) takes antennas a0 + g NLD + j, j < NLD, the same for H
-            // and Y, so every MFMA contracts matching antennas
-            Wt hr[F][NLD], hi[F][NLD], yr[NLD], yi[NLD];
-            const uint32_t ab = (uint32_t)(a0 + g * NLD);
+        // H rows that are whole 128-byte lines stream non-temporally (one
+        // loop per cache policy: the policy is part of the instruction)
+        auto gram_loop = [&](auto hcp) {
+            for (int a0 = 0; a0 < Nbs; a0 += KBG) {
+                // range-checked loads: all loads of the block in flight together;
+                // lane (g, n) takes antennas a0 + g NLD + j, j < NLD, the same for H
+                // and Y, so every MFMA contracts matching antennas
+                Wt hr[F][NLD], hi[F][NLD], yr[NLD], yi[NLD];
+                const uint32_t ab = (uint32_t)(a0 + g * NLD);
 #pragma unroll
-            for (int j = 0; j < NLD; ++j) {
+                for (int j = 0; j < NLD; ++j) {
 #pragma unroll
-                for (int f = 0; f < F; ++f) CxB<IOT>::load(bH, hl[f] + (ab + j) * hrow, hr[f][j], hi[f][j]);
-                CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
-            }
-#pragma unroll
-            for (int u = 0; u < NSUB; ++u) {
-                gfrag Xr[F], Xi[F], nXi[F];
-#pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    Xr[f] = OG::pack(&hr[f][u * KPLG], sH);
-                    Xi[f] = OG::pack(&hi[f][u * KPLG], sH);
-                    nXi[f] = OG::neg(Xi[f]);
+                    for (int f = 0; f < F; ++f) CxB<IOT>::template load<decltype(hcp)::value>(bH, hl[f] + (ab + j) * hrow, hr[f][j], hi[f][j]);
+                    CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
                 }
-                const gfrag Yr = OG::pack(&yr[u * KPLG], sY), Yi = OG::pack(&yi[u * KPLG], sY);
-                int q = 0;
 #pragma unroll
-                for (int f1 = 0; f1 < F; ++f1) {
+                for (int u = 0; u < NSUB; ++u) {
+                    gfrag Xr[F], Xi[F], nXi[F];
 #pragma unroll
-                    for (int f2 = f1; f2 < F; ++f2) {
-                        if (NW == 1 || q % NW == wave) {
-                            const int s = q / NW;
-                            gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
-                            gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
-                            gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
-                            gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
+                    for (int f = 0; f < F; ++f) {
+                        Xr[f] = OG::pack(&hr[f][u * KPLG], sH);
+                        Xi[f] = OG::pack(&hi[f][u * KPLG], sH);
+                        nXi[f] = OG::neg(Xi[f]);
+                    }
+                    const gfrag Yr = OG::pack(&yr[u * KPLG], sY), Yi = OG::pack(&yi[u * KPLG], sY);
+                    int q = 0;
+#pragma unroll
+                    for (int f1 = 0; f1 < F; ++f1) {
+#pragma unroll
+                        for (int f2 = f1; f2 < F; ++f2) {
+                            if (NW == 1 || q % NW == wave) {
+                                const int s = q / NW;
+                                gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
+                                gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
+                                gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
+                                gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
+                            }
+                            ++q;
                         }
-                        ++q;
                     }
-                }
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    if (NW == 1 || f % NW == wave) {
-                        const int s = f / NW;
-                        gBr[s] = OG::mfma(Xr[f], Yr, gBr[s]);
-                        gBr[s] = OG::mfma(Xi[f], Yi, gBr[s]);
-                        gBi[s] = OG::mfma(Xr[f], Yi, gBi[s]);
-                        gBi[s] = OG::mfma(nXi[f], Yr, gBi[s]);
+                    for (int f = 0; f < F; ++f) {
+                        if (NW == 1 || f % NW == wave) {
+                            const int s = f / NW;
+                            gBr[s] = OG::mfma(Xr[f], Yr, gBr[s]);
+                            gBr[s] = OG::mfma(Xi[f], Yi, gBr[s]);
+                            gBi[s] = OG::mfma(Xr[f], Yi, gBi[s]);
+                            gBi[s] = OG::mfma(nXi[f], Yr, gBi[s]);
+                        }
                     }
                 }
             }
-        }
+        };
+        if (hrow % 128u == 0) gram_loop(std::integral_constant<int, CP_STREAM>{});
+        else gram_loop(std::integral_constant<int, 0>{});
 
         // scale back (fp8), add sigma^2, mirror into LDS
         const Wt invH = (Wt)ldexpf(1.f, -eH), invY = (Wt)ldexpf(1.f, -eY);
