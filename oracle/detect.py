@@ -21,6 +21,11 @@ What is computed and where the paper defines it
                    format, the (P)CG solve with an optional FP64 residual
                    refresh, optional FP64 iterative refinement through H,
                    then the QAM slicer.
+  * lanczos_kappa(): the condition number of the iteration matrix estimated
+                   from the CG coefficients alpha_i, beta_i (the Lanczos
+                   tridiagonal of CG, a textbook identity the paper does not
+                   use; it feeds eq. heuristic / eq. heuristic_bj with a
+                   per-channel kappa instead of E{kappa}).
 
 Readings where the paper is silent:
   R-alpha  alpha and beta use the real parts of the inner products (A is
@@ -412,12 +417,13 @@ def _select(mask, a, b):
     return np.where(mask, a, b)
 
 
-def fp_cg(A, b, iters: int, sched: Schedule = FP64, mv=None, A_ref=None, trace=None):
+def fp_cg(A, b, iters: int, sched: Schedule = FP64, mv=None, A_ref=None, trace=None, coeffs=None):
     """Alg. 2 (FP-CG).  Returns (x, broken) with broken a (B,) bool array.
 
     A is the Gram matrix in u_W (used for the FP64 refresh); ``mv`` is the u_MV
     product (defaults to MatVec(A, sched)); ``trace``, if a list, receives
-    (x_i, r_i) after every iteration.
+    (x_i, r_i) after every iteration; ``coeffs``, if a list, receives
+    (alpha_i, beta_i, live_i) after every iteration, each shaped (B, 1, R).
     """
     P = _Prec(sched)
     mv = mv if mv is not None else MatVec(A, sched)
@@ -444,6 +450,8 @@ def fp_cg(A, b, iters: int, sched: Schedule = FP64, mv=None, A_ref=None, trace=N
         p = _select(live, P.axpy(beta, p, r), p)               # p = r + beta p
         if trace is not None:
             trace.append((x.copy(), r.copy()))
+        if coeffs is not None:
+            coeffs.append((np.real(alpha).copy(), np.real(beta).copy(), live.copy()))
     return x, broken
 
 
@@ -529,7 +537,8 @@ def bj_inverse(A, L: int, work: str = "fp64"):
     return fl(M, work), not_pd
 
 
-def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, A_ref=None, trace=None):
+def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, A_ref=None, trace=None,
+             coeffs=None):
     """Alg. 3 (FP-BJ-CG), left-preconditioned.  Returns (x, broken).
 
     variant 0 follows the printed algorithm (rho_{i-1} = r^H p for alpha and for
@@ -539,7 +548,7 @@ def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, 
     Thm 4 analyses; in exact arithmetic all three give the same iterates.
     """
     if sched.variant == 2:
-        return fp_bj_cg_split(A, b, iters, L, sched, A_ref=A_ref, trace=trace)[:2]
+        return fp_bj_cg_split(A, b, iters, L, sched, A_ref=A_ref, trace=trace, coeffs=coeffs)[:2]
     P = _Prec(sched)
     mv = mv if mv is not None else MatVec(A, sched)
     if M is None:
@@ -570,6 +579,8 @@ def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, 
         rho_carry = rho
         if trace is not None:
             trace.append((x.copy(), r.copy()))
+        if coeffs is not None:
+            coeffs.append((np.real(alpha).copy(), np.real(beta).copy(), live.copy()))
     return x, broken
 
 
@@ -577,7 +588,7 @@ def fp_bj_cg(A, b, iters: int, L: int, sched: Schedule = FP64, mv=None, M=None, 
 # QAM slicer and bit errors
 # --------------------------------------------------------------------------
 def fp_bj_cg_split(A, b, iters: int, L: int, sched: Schedule = FP64, T=None, Abar=None, mv=None, A_ref=None,
-                   trace=None):
+                   trace=None, coeffs=None):
     """Alg. 3 in its symmetric form: CG (Alg. 2 steps) on A_bar x_bar = b_bar,
     then x = T^H x_bar.  Returns (x, broken, T, A_bar)."""
     W = sched.work if not _is_exact(A) else "fp64"
@@ -587,10 +598,63 @@ def fp_bj_cg_split(A, b, iters: int, L: int, sched: Schedule = FP64, T=None, Aba
         Abar = split_system(A, T, W)
     mv = mv if mv is not None else MatVec(Abar, sched)
     bb = fl(T @ b, W) if not _is_exact(b) else T @ b
-    xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv, A_ref=Abar, trace=trace)
+    xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv, A_ref=Abar, trace=trace, coeffs=coeffs)
     Th = np.conj(np.swapaxes(T, -1, -2))
     x = fl(Th @ xb, W) if not _is_exact(xb) else Th @ xb
     return x, broken, T, Abar
+
+
+def lanczos_tridiagonal(alphas, betas):
+    """The Lanczos tridiagonal of m CG steps of one column (textbook identity,
+    e.g. Saad, Iterative Methods for Sparse Linear Systems, Sec. 6.7.3): with
+    the coefficients alpha_1..alpha_m (step sizes) and beta_1..beta_m (the
+    ratios rho_i / rho_{i-1}),
+        T[0, 0] = 1 / alpha_1,
+        T[i, i] = 1 / alpha_{i+1} + beta_i / alpha_i          (i = 1..m-1),
+        T[i-1, i] = T[i, i-1] = sqrt(beta_i) / alpha_i        (i = 1..m-1).
+    The eigenvalues of T (Ritz values) approximate those of the iteration
+    matrix (A; M_d A for the left-preconditioned Alg. 3; A_bar for its
+    symmetric form) and lie inside its spectrum."""
+    a = np.asarray(alphas, dtype=np.float64)
+    bt = np.asarray(betas, dtype=np.float64)
+    m = a.size
+    T = np.zeros((m, m))
+    T[0, 0] = 1.0 / a[0]
+    for i in range(1, m):
+        T[i, i] = 1.0 / a[i] + bt[i - 1] / a[i - 1]
+        T[i - 1, i] = T[i, i - 1] = math.sqrt(bt[i - 1]) / a[i - 1]
+    return T
+
+
+def lanczos_kappa(coeffs, R_valid=None):
+    """Per channel: the largest, over its received-vector columns, of
+    lambda_max(T) / lambda_min(T) with T the Lanczos tridiagonal of the
+    column's CG steps taken before any breakdown (coeffs from fp_cg /
+    fp_bj_cg / detect).  A column without a step gives no estimate; a
+    channel without any estimate gets NaN.  Each column's ratio is at most
+    the iteration matrix's condition number (the Ritz values interlace)."""
+    if not coeffs:
+        raise ValueError("no CG steps recorded")
+    al = np.stack([c[0] for c in coeffs], axis=0)[:, :, 0, :]     # (I, B, R)
+    be = np.stack([c[1] for c in coeffs], axis=0)[:, :, 0, :]
+    lv = np.stack([c[2] for c in coeffs], axis=0)[:, :, 0, :]
+    I, Bn, R = al.shape
+    R_valid = R if R_valid is None else R_valid
+    out = np.full(Bn, np.nan)
+    for ch in range(Bn):
+        best = np.nan
+        for j in range(R_valid):
+            m = 0
+            while m < I and lv[m, ch, j] and al[m, ch, j] > 0:
+                m += 1
+            if m == 0:
+                continue
+            # the last step's beta only enters through a further step
+            ev = np.linalg.eigvalsh(lanczos_tridiagonal(al[:m, ch, j], be[:m, ch, j]))
+            k = ev[-1] / ev[0] if ev[0] > 0 else np.inf
+            best = k if np.isnan(best) else max(best, k)
+        out[ch] = best
+    return out
 
 
 def _gray(n):
@@ -645,8 +709,11 @@ class Result:
     b: np.ndarray          # matched filter in u_W
 
 
-def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64) -> Result:
-    """Gram + matched filter -> (BJ setup) -> (P)CG -> (refinement) -> slicer."""
+def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64, coeffs=None) -> Result:
+    """Gram + matched filter -> (BJ setup) -> (P)CG -> (refinement) -> slicer.
+
+    ``coeffs``, if a list, receives the CG coefficients of the first solve
+    (the one of b; see fp_cg)."""
     H = np.asarray(H, dtype=np.complex128)
     Y = np.asarray(Y, dtype=np.complex128)
     Bn = H.shape[0]
@@ -665,17 +732,17 @@ def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64)
         flags |= np.where(not_pd, FLAG_BLOCK_NOT_PD, 0).astype(np.uint32)
     mv = MatVec(Abar if split else A, sched, flags)
 
-    def solve(rhs, exact_back=False):
+    def solve(rhs, exact_back=False, coeffs=None):
         if split:
             bb = fl(T @ rhs, sched.work)
-            xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv)
+            xb, broken = fp_cg(Abar, bb, iters, sched, mv=mv, coeffs=coeffs)
             x = np.conj(np.swapaxes(T, -1, -2)) @ xb
             return (x if exact_back else fl(x, sched.work)), broken
         if L:
-            return fp_bj_cg(A, rhs, iters, L, sched, mv=mv, M=M)
-        return fp_cg(A, rhs, iters, sched, mv=mv)
+            return fp_bj_cg(A, rhs, iters, L, sched, mv=mv, M=M, coeffs=coeffs)
+        return fp_cg(A, rhs, iters, sched, mv=mv, coeffs=coeffs)
 
-    x, broken = solve(b)
+    x, broken = solve(b, coeffs=coeffs)
     flags |= np.where(broken, FLAG_BREAKDOWN, 0).astype(np.uint32)
     slice_prec = sched.work
     if sched.refine_steps:

@@ -324,6 +324,7 @@ def test_operand_rounding_bitwise(fmt):
 # --------------------------------------------------------------- full-size sampled parity
 @pytest.mark.parametrize("cfg,sched,L,iters,refresh,variant", [
     ("c2", "bf16", 0, 16, 0, 0), ("c2", "fp32", 0, 16, 0, 0), ("c2", "fp64", 0, 16, 0, 0),
+    ("c2", "fp16", 4, 11, 0, 2), ("c2", "fp64", 0, 15, 0, 0),  # the timed launches
     ("c2", "bf16", 8, 12, 0, 2), ("c3", "fp16", 8, 16, 4, 0), ("c3", "fp16", 8, 16, 4, 2), ("c3", "fp64", 0, 24, 0, 0),
 ])
 def test_full_size_sampled(cfg, sched, L, iters, refresh, variant):
