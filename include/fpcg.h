@@ -167,6 +167,35 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream,
                         const fpcg_schedule* sched,
                         void* xhat, uint8_t* labels, uint32_t* flags);
 
+/* The detector over a subset of the batch, with an optional per-channel
+ * condition-number estimate: the input for choosing each channel's operand
+ * format with eq. heuristic / eq. heuristic_bj from its own kappa instead of
+ * E{kappa} (the footnote to eq. heuristic allows either).
+ *   Arguments B .. flags as fpcg_detect (all arrays cover the whole batch).
+ *   chan_idx: NULL, or a device array of n_idx channel indices; only those
+ *     channels are detected and only their outputs (xhat, labels, flags,
+ *     kappa) are written; indices outside [0, B) are skipped.  n_idx is
+ *     ignored when chan_idx is NULL (all B channels).
+ *   kappa: NULL, or a device array of B floats: for each detected channel,
+ *     the largest over its received vectors of lambda_max(T) / lambda_min(T),
+ *     T the Lanczos tridiagonal of the CG coefficients of the first solve
+ *     (T[0][0] = 1/alpha_1, T[i][i] = 1/alpha_{i+1} + beta_i/alpha_i,
+ *     T[i-1][i]^2 = beta_i/alpha_i^2, from the first min(iters, 32) steps
+ *     taken before any breakdown).  It estimates the condition number of
+ *     the iteration matrix (A without preconditioner, M_d A or A_bar with
+ *     it) from below; NaN when no step was taken (iters = 0, breakdown in
+ *     the first step).  Needs a stream-ordered workspace of
+ *     n * R * iters * 8 bytes (FPCG_E_NOMEM if it cannot be had).
+ *   Always one workgroup per channel (the launch form setting is not used).
+ *   Errors as fpcg_detect, plus FPCG_E_INVAL for n_idx outside [0, 2^31). */
+fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
+                           int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                           const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                           int32_t qam_order, int32_t iters, int32_t block_L,
+                           const fpcg_schedule* sched,
+                           void* xhat, uint8_t* labels, uint32_t* flags,
+                           const int32_t* chan_idx, int64_t n_idx, float* kappa);
+
 /* QAM slicer on its own (the detector's epilogue): nearest unit-energy
  * square-QAM point per complex value, decided in FP32 (x_c64 != 0) or FP64.
  * Per axis j = clamp(floor((v nu + m) / 2), 0, m - 1), nu = sqrt(2 (Q-1) / 3),

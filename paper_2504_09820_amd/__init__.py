@@ -97,6 +97,9 @@ def lib():
     L.fpcg_check.restype = st
     L.fpcg_detect.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule), vp, vp, vp]
     L.fpcg_detect.restype = st
+    L.fpcg_detect_ex.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule),
+                                 vp, vp, vp, vp, i64, vp]
+    L.fpcg_detect_ex.restype = st
     L.fpcg_slice.argtypes = [vp, i64, vp, i32, i32, vp]
     L.fpcg_slice.restype = st
     L.fpcg_round.argtypes = [vp, i64, vp, i32, ctypes.c_float, vp]
@@ -198,12 +201,15 @@ def _stream_handle(stream, device):
 
 def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Schedule" = "fp64",
            refresh_every: int = 0, refine_steps: int = 0, variant: int = 0,
-           ctx: Optional[Context] = None, stream=None, out=None):
+           ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None):
     """Run the detector on device tensors.
 
     H (B, Nbs, K) and Y (B, Nbs, R): complex64 or complex128 CUDA tensors,
     contiguous, same dtype; sigma2 (B,) float64 CUDA tensor.  Returns
     (xhat (B, K, R) like H, labels (B, K, R) uint8, flags (B,) int32 bits).
+    chan_idx (int32 CUDA tensor) restricts the launch to those channels;
+    kappa (float32 CUDA tensor of B) receives per-channel condition-number
+    estimates (fpcg_detect_ex).
     """
     import torch
 
@@ -232,6 +238,22 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         flags = torch.empty((B,), dtype=torch.int32, device=H.device)
     else:
         xhat, labels, flags = out
+    if chan_idx is not None or kappa is not None:
+        if chan_idx is not None and (chan_idx.dtype != torch.int32 or not chan_idx.is_cuda):
+            raise TypeError("chan_idx must be an int32 CUDA tensor")
+        if kappa is not None and (kappa.dtype != torch.float32 or not kappa.is_cuda or kappa.shape != (B,)):
+            raise TypeError("kappa must be a float32 CUDA tensor of shape (B,)")
+        idx = chan_idx.contiguous() if chan_idx is not None else None
+        _check(lib().fpcg_detect_ex(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
+                                    ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                    1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
+                                    qam, iters, L, ctypes.byref(sched),
+                                    ctypes.c_void_p(xhat.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                                    ctypes.c_void_p(flags.data_ptr()),
+                                    ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
+                                    idx.numel() if idx is not None else 0,
+                                    ctypes.c_void_p(kappa.data_ptr() if kappa is not None else 0)))
+        return xhat, labels, flags
     _check(lib().fpcg_detect(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                              ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                              1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),

@@ -51,6 +51,11 @@ struct FusedParams {
     int32_t refresh_every, refine_steps, variant;
     double nu;     // sqrt(2 (Q - 1) / 3)
     int32_t m, bits;
+    // optional: the launch's channels as indices into the batch (NULL: all B
+    // in order; grid x = their count), and a record of the first solve's CG
+    // coefficients, [launch position][column][iteration][alpha, beta] (NULL: none)
+    const int32_t* chan_idx;
+    float* ab_hist;
 };
 
 // Lanes of the symmetric block-Jacobi transform.  Pass 1 (rows) needs rows
@@ -1318,8 +1323,10 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             const bool ok = live && __builtin_isfinite(ph) && __builtin_isfinite(rho_prev) && ph > 0 && rho_prev > 0;
             if (live && !ok && colv) broken = true;
             live = ok;
+            Wt alpha_rec = 0, beta_rec = 0;             // the step's coefficients (0 once frozen)
             if (live) {
                 const Wt alpha = rho_prev / ph;
+                alpha_rec = alpha;
                 if constexpr (!xreg) {
 #pragma unroll
                     for (int e = 0; e < SH; ++e) { xr_[e] = sXr[e * NT + tid]; xi_[e] = sXi[e * NT + tid]; }
@@ -1399,6 +1406,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             const Wt rho_new = v[0];
             if (live) {
                 const Wt beta = rho_new / rho_prev;
+                beta_rec = beta;
 #pragma unroll
                 for (int e = 0; e < SH; ++e) {
                     pr[e] = fma(beta, pr[e], zr[e]);
@@ -1406,6 +1414,12 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 }
             }
             rho_cur = rho_new;
+            if (MODE == MODE_FULL && P.ab_hist && pass == 0 && g == 0 && wave == 0 && colv) {
+                // one lane per received-vector column records alpha_i, beta_i
+                float* h = P.ab_hist + (((int64_t)blockIdx.x * R + col) * P.iters + (it - 1)) * 2;
+                h[0] = (float)alpha_rec;
+                h[1] = (float)beta_rec;
+            }
         }
         if (broken) myflag |= FLAG_BREAKDOWN;
         // ------------------------------------------------ back-transform and refinement bookkeeping
@@ -1497,8 +1511,12 @@ template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(fused_waves<KP, FMT, LB, SPLIT, REF, IOT>())))
 void fused_kernel(const FusedParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
-    detect_channel<KP, NW, FMT, LB, SPLIT, REF, IOT, MODE_FULL>(P, blockIdx.x, blockIdx.y, smem, smem, nullptr,
-                                                                 threadIdx.x);
+    int64_t ch = blockIdx.x;
+    if (P.chan_idx) {
+        ch = P.chan_idx[blockIdx.x];                  // uniform: the whole workgroup skips together
+        if (ch < 0 || ch >= P.B) return;
+    }
+    detect_channel<KP, NW, FMT, LB, SPLIT, REF, IOT, MODE_FULL>(P, ch, blockIdx.y, smem, smem, nullptr, threadIdx.x);
 }
 
 // Pipelined form for one-wave channels: a persistent workgroup of two waves

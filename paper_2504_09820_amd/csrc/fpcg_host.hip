@@ -143,6 +143,13 @@ struct ScopedDevice {
 __global__ void zero_u32(uint32_t* p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
+// p[idx[i]] = 0 for the n indices in [0, B)
+__global__ void zero_u32_at(uint32_t* p, const int32_t* idx, int64_t n, int64_t B) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = idx[i];
+        if (c >= 0 && c < B) p[c] = 0u;
+    }
+}
 
 static inline unsigned grid_for(int64_t n, int threads) {
     int64_t b = (n + threads - 1) / threads;
@@ -195,10 +202,12 @@ std::vector<int> launch_forms(const Plan& plan, int32_t R, int32_t io_c64) {
 fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int form, int64_t B,
                                int32_t Nbs, int32_t K, int32_t R, const void* H, const void* Y, int32_t io_c64,
                                const double* sigma2, int32_t qam, int32_t iters, void* xhat, uint8_t* labels,
-                               uint32_t* flags) {
+                               uint32_t* flags, const LaunchExtra* ex) {
     const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
     if (!e) return fail(FPCG_E_UNSUPPORTED, "variant missing");
-    if (B == 0) return FPCG_OK;
+    const bool indexed = ex && ex->chan_idx;
+    const int64_t n = indexed ? ex->n : B;           // workgroups along x
+    if (B == 0 || n == 0) return FPCG_OK;
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         for (const auto& t : table())
@@ -209,7 +218,10 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
                                                   (int)t.lds(sp != 0, r != 0, 1));
     });
     if (flags && R > 16) {   // several workgroups per channel OR their flags together
-        hipLaunchKernelGGL(zero_u32, dim3(grid_for(B, 256)), dim3(256), 0, stream, flags, B);
+        if (indexed)
+            hipLaunchKernelGGL(zero_u32_at, dim3(grid_for(n, 256)), dim3(256), 0, stream, flags, ex->chan_idx, n, B);
+        else
+            hipLaunchKernelGGL(zero_u32, dim3(grid_for(B, 256)), dim3(256), 0, stream, flags, B);
     }
     FusedParams p;
     p.H = H; p.Y = Y; p.sigma2 = sigma2; p.xhat = xhat; p.labels = labels; p.flags = flags;
@@ -221,10 +233,12 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
     p.bits = 0;
     while ((1 << p.bits) < p.m) ++p.bits;
     p.nu = std::sqrt(2.0 * (qam - 1) / 3.0);
+    p.chan_idx = indexed ? ex->chan_idx : nullptr;
+    p.ab_hist = ex ? ex->ab_hist : nullptr;
     const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
     const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
     const int ncb = (R + 15) / 16;
-    if (!ref && e->pipe_fn[sp] && form == FPCG_LAUNCH_PIPELINED) {
+    if (!ref && !ex && e->pipe_fn[sp] && form == FPCG_LAUNCH_PIPELINED) {
         // pipelined form: persistent two-wave workgroups, as many as fit at once
         const size_t lds = e->pipe_lds(sp != 0, p.refresh_every);
         const int per_cu = pipe_occupancy(ctx->device, e->pipe_fn[sp], lds);
@@ -237,7 +251,7 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
             return FPCG_OK;
         }
     }
-    dim3 grid((unsigned)B, (unsigned)ncb);
+    dim3 grid((unsigned)n, (unsigned)ncb);
     const size_t lds = e->lds(sp != 0, ref != 0, p.refresh_every);   // within 160 KiB (check_args)
     e->launch[sp][ref](p, grid, lds, stream);
     hipError_t err = hipGetLastError();
@@ -338,6 +352,40 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int
     ScopedDevice sd(ctx->device);
     return launch_detect(ctx, (hipStream_t)stream, plan, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters,
                          xhat, labels, flags);
+}
+
+fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
+                           const void* Y, int32_t io_c64, const double* sigma2, int32_t qam_order, int32_t iters,
+                           int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags,
+                           const int32_t* chan_idx, int64_t n_idx, float* kappa) {
+    clear_error();
+    if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    Plan plan;
+    fpcg_status st = check_args(B, Nbs, K, R, qam_order, iters, block_L, sched, &plan);
+    if (st != FPCG_OK) return st;
+    if (chan_idx && (n_idx < 0 || n_idx > 0x7fffffffLL))
+        return fail(FPCG_E_INVAL, "n_idx=%lld out of range [0, 2^31-1]", (long long)n_idx);
+    const int64_t n = chan_idx ? n_idx : B;
+    if (n > 0 && (!H || !Y || !sigma2 || !xhat || !labels))
+        return fail(FPCG_E_INVAL, "H, Y, sigma2, xhat and labels must be non-NULL");
+    if (B == 0 || n == 0) return FPCG_OK;
+    ScopedDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    LaunchExtra ex;
+    ex.chan_idx = chan_idx;
+    ex.n = n;
+    const size_t hist_bytes = kappa && iters > 0 ? (size_t)n * R * iters * 2 * sizeof(float) : 0;
+    if (hist_bytes) {
+        void* h = nullptr;
+        if (hipMallocAsync(&h, hist_bytes, s) != hipSuccess || !h)
+            return fail(FPCG_E_NOMEM, "coefficient record of %zu bytes", hist_bytes);
+        ex.ab_hist = static_cast<float*>(h);
+    }
+    st = launch_detect_form(ctx, s, plan, FPCG_LAUNCH_FUSED, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters,
+                            xhat, labels, flags, &ex);
+    if (st == FPCG_OK && kappa) st = launch_kappa(s, ex.ab_hist, n, R, iters, chan_idx, B, kappa);
+    if (ex.ab_hist) (void)hipFreeAsync(ex.ab_hist, s);
+    return st;
 }
 
 fpcg_status fpcg_slice(void* stream, int64_t n, const void* x, int32_t x_c64, int32_t qam_order, uint8_t* labels) {

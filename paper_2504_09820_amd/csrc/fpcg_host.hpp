@@ -39,11 +39,22 @@ using TuneKey = fpcg_tune_key;
 TuneKey tune_key(const Plan& plan, int32_t R, int32_t io_c64);
 // launch forms built for a plan (FPCG_LAUNCH_FUSED first)
 std::vector<int> launch_forms(const Plan& plan, int32_t R, int32_t io_c64);
-// one launch in the given form (FPCG_LAUNCH_FUSED or FPCG_LAUNCH_PIPELINED)
+// a launch over a subset of the batch (chan_idx: n indices, NULL = all B) and
+// an optional record of the CG coefficients (n x R x iters x 2 floats)
+struct LaunchExtra {
+    const int32_t* chan_idx = nullptr;
+    int64_t n = 0;
+    float* ab_hist = nullptr;
+};
+// one launch in the given form (FPCG_LAUNCH_FUSED or FPCG_LAUNCH_PIPELINED;
+// a launch with extras always runs fused)
 fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int form, int64_t B,
                                int32_t Nbs, int32_t K, int32_t R, const void* H, const void* Y, int32_t io_c64,
                                const double* sigma2, int32_t qam, int32_t iters, void* xhat, uint8_t* labels,
-                               uint32_t* flags);
+                               uint32_t* flags, const LaunchExtra* ex = nullptr);
+// per-channel kappa estimates from a coefficient record (fpcg_kappa.hip)
+fpcg_status launch_kappa(hipStream_t stream, const float* hist, int64_t n, int32_t R, int32_t iters,
+                         const int32_t* chan_idx, int64_t B, float* kappa);
 
 fpcg_status launch_detect(const fpcg_ctx* ctx, hipStream_t stream, const Plan& plan, int64_t B, int32_t Nbs, int32_t K,
                           int32_t R, const void* H, const void* Y, int32_t io_c64, const double* sigma2, int32_t qam,

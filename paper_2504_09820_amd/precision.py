@@ -8,6 +8,13 @@ once per workload class from a sample of its channels (the expectation that
 the heuristic's footnote allows), then the library's fpcg_select_precision
 picks the cheapest format below the bound.  This is calibration done on the
 host before any detection; nothing here runs per channel on the hot path.
+
+Per channel (the alternative the footnote also allows): a detection with a
+kappa output (fpcg_detect_ex) estimates each channel's kappa from its CG
+coefficients; formats_per_channel() applies the same bound to each estimate
+and detect_adaptive() runs each group of channels in its format, one
+launch per format over that group's channel indices (H and Y stay where
+they are).
 """
 from __future__ import annotations
 
@@ -42,3 +49,55 @@ def choose_format(K: int, kappa: float, allow_fp8: bool = False) -> tuple[str, f
     from . import select_precision
 
     return select_precision(K, kappa, allow_fp8)
+
+
+FORMATS = ("fp8", "fp16", "bf16", "fp32", "fp64")
+
+
+def formats_per_channel(kappa, K: int, allowed=("fp16", "fp32", "fp64"), fallback: str = "fp64") -> np.ndarray:
+    """Per channel, the cheapest format in `allowed` whose unit roundoff meets
+    u < 1 / (K^1.5 sqrt(kappa)); channels without an estimate (NaN) or with
+    none of `allowed` meeting the bound get `fallback`.  Returns an object
+    array of format names."""
+    u = {"fp8": 2.0 ** -4, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
+    order = [f for f in FORMATS if f in allowed]
+    k = np.asarray(kappa.cpu() if hasattr(kappa, "cpu") else kappa, dtype=np.float64)
+    bound = 1.0 / (float(K) ** 1.5 * np.sqrt(np.where(np.isfinite(k) & (k >= 1.0), k, np.nan)))
+    out = np.full(k.shape, fallback, dtype=object)
+    done = ~np.isfinite(bound)
+    for f in order:
+        pick = ~done & (u[f] < bound)
+        out[pick] = f
+        done |= pick
+    return out
+
+
+def detect_adaptive(H, Y, sigma2, qam: int, iters: int, L: int, formats, variant: int = 2, ctx=None, stream=None,
+                    out=None):
+    """Detect every channel in its own format: one fpcg_detect_ex launch per
+    distinct format over that format's channel indices.  `formats` is a
+    length-B sequence of format names (formats_per_channel).  Returns
+    (xhat, labels, flags, groups) with groups {format: number of channels}."""
+    import torch
+
+    from . import detect
+
+    B, _, K = H.shape
+    R = Y.shape[2]
+    f = np.asarray(formats, dtype=object)
+    if f.shape != (B,):
+        raise ValueError("one format per channel")
+    if out is None:
+        out = (torch.empty((B, K, R), dtype=H.dtype, device=H.device),
+               torch.empty((B, K, R), dtype=torch.uint8, device=H.device),
+               torch.empty((B,), dtype=torch.int32, device=H.device))
+    groups = {}
+    for name in FORMATS:
+        sel = np.nonzero(f == name)[0]
+        if sel.size == 0:
+            continue
+        idx = torch.from_numpy(sel.astype(np.int32)).to(H.device)
+        detect(H, Y, sigma2, qam, iters, L, name, variant=variant if L else 0, ctx=ctx, stream=stream, out=out,
+               chan_idx=idx)
+        groups[name] = int(sel.size)
+    return out[0], out[1], out[2], groups
