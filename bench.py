@@ -126,6 +126,166 @@ def write_traffic(args, fetch_csv, write_csv):
     log(f"wrote {path}: {rec['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch")
 
 
+def _kappa_abar(H, sigma2, L):
+    """Exact 2-norm condition numbers of the iteration matrix (A, or T A T^H
+    with L x L Cholesky blocks) of each channel, numpy eigvalsh."""
+    H = np.asarray(H, dtype=np.complex128)
+    K = H.shape[2]
+    A = np.conj(np.swapaxes(H, -1, -2)) @ H + np.asarray(sigma2)[:, None, None] * np.eye(K)
+    if L:
+        T = np.zeros_like(A)
+        for b in range(0, K, L):
+            C = np.linalg.cholesky(A[:, b:b + L, b:b + L])
+            T[:, b:b + L, b:b + L] = np.linalg.inv(C)
+        A = T @ A @ np.conj(np.swapaxes(T, -1, -2))
+    ev = np.linalg.eigvalsh(A)
+    return ev[:, -1] / ev[:, 0]
+
+
+def kappa_bench(args, steps=30, rounds=3):
+    """Per-channel precision selection with kappa estimated on the device from
+    the CG coefficients (fpcg_detect_ex).  c2: the estimate's cost on top of
+    the timed detection, its accuracy against the exact kappa of the
+    iteration matrix on a sample, and the oracle's estimate timed on the host.
+    c3's shape with mixed correlation (L = 8, symmetric form, I = 16): one
+    estimating launch in the heuristic's pick for E{kappa}, then each channel
+    in the cheapest format its own estimate allows (fp16 or fp32), against
+    all channels in the single format; bit error rates of both against the
+    transmitted symbols.  One JSON line."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+    from paper_2504_09820_amd import precision
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = fp.Context(0)
+    res = {"mode": "kappa"}
+
+    def timed(fn, n=steps):
+        torch.cuda.synchronize()
+        time.sleep(IDLE_S)
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+
+    # ---------------------------------------------------------------- c2
+    c = W.CONFIGS["c2"]
+    B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
+    wl = W.draw(B, Nbs, K, R, q, c["snr_db"], c["zeta"], c["zeta"], seed=2504_09820 * 10 + 2,
+                normalization=c["normalization"])
+    H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    s2 = torch.from_numpy(wl.sigma2).to(dev)
+    out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
+           torch.empty((B,), dtype=torch.int32, device=dev))
+    kap = torch.empty((B,), dtype=torch.float32, device=dev)
+    plain = lambda: fp.detect(H, Y, s2, q, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=stream)
+    withk = lambda: fp.detect(H, Y, s2, q, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=stream, kappa=kap)
+    tp, tk = [], []
+    for _ in range(rounds):
+        tp.append(timed(plain))
+        tk.append(timed(withk))
+    tp, tk = np.concatenate(tp), np.concatenate(tk)
+    log(f"c2 fp16 L=4 I=11: detection p50 {np.median(tp):.4f} ms, with kappa p50 {np.median(tk):.4f} ms")
+    withk()
+    torch.cuda.synchronize()
+    kg = kap.cpu().numpy().astype(np.float64)
+    smp = np.random.default_rng(0).choice(B, 512, replace=False)
+    kx = _kappa_abar(wl.H[smp].astype(np.complex64), wl.sigma2[smp], 4)
+    ratio = kg[smp] / kx
+    log(f"c2 kappa estimate / exact kappa(A_bar) on 512 channels: median {np.median(ratio):.4f}, "
+        f"min {ratio.min():.4f}, max {ratio.max():.4f}")
+    res["c2"] = {"schedule": "fp16", "L": 4, "variant": 2, "iters": 11, "B": B,
+                 "detect_p50_ms": round(float(np.median(tp)), 5), "detect_mean_ms": round(float(np.mean(tp)), 5),
+                 "detect_with_kappa_p50_ms": round(float(np.median(tk)), 5),
+                 "detect_with_kappa_mean_ms": round(float(np.mean(tk)), 5),
+                 "kappa_overhead": round(float(np.median(tk) / np.median(tp) - 1.0), 4),
+                 "estimate_over_exact": {"median": round(float(np.median(ratio)), 4), "min": round(float(ratio.min()), 4),
+                                         "max": round(float(ratio.max()), 4), "channels": 512},
+                 "exact_kappa_abar_median": round(float(np.median(kx)), 3)}
+    # the oracle's estimate on the host: its FP64 CG coefficients of 64 channels, one thread
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import detect as D
+
+        n_o = 64
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            co = []
+            D.detect(wl.H[:n_o].astype(np.complex64).astype(np.complex128), wl.Y[:n_o].astype(np.complex64).astype(np.complex128),
+                     wl.sigma2[:n_o], q, 11, 4, D.schedule("fp64", variant=2), coeffs=co)
+            ko = D.lanczos_kappa(co)
+            dt = time.perf_counter() - t1
+        res["c2"]["cpu_baseline"] = {"value": round(n_o / dt, 1), "unit": "channels/s", "cores": 1, "kind": "oracle",
+                                     "sample": f"{n_o} channels: FP64 FP-BJ-CG (symmetric form, L=4, I=11) with its "
+                                               f"coefficients recorded, then the Lanczos estimate ({dt:.2f} s)"}
+        log(f"oracle: {n_o / dt:.1f} channels/s (detection + estimate, one thread)")
+        del ko
+    del H, Y, s2, out, kap
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- c3 shape, mixed conditioning
+    # c3's shape (Nbs = 256, K = 64, 15 dB) with the serving workload's spread of
+    # correlation: eight equal groups at zeta = 0, 0.125, ..., 0.875
+    c = W.CONFIGS["c3"]
+    B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
+    L, it = 8, 16
+    parts = [W.draw(B // 8, Nbs, K, R, q, c["snr_db"], z, z, seed=2504_09820 * 10 + 30 + g, normalization=c["normalization"])
+             for g, z in enumerate(0.125 * np.arange(8))]
+    wl = W.Workload(H=np.concatenate([p.H for p in parts]), Y=np.concatenate([p.Y for p in parts]),
+                    labels=np.concatenate([p.labels for p in parts]), X=np.concatenate([p.X for p in parts]),
+                    sigma2=np.concatenate([p.sigma2 for p in parts]), q=q, snr_db=np.concatenate([p.snr_db for p in parts]))
+    del parts
+    H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    s2 = torch.from_numpy(wl.sigma2).to(dev)
+    tx = torch.from_numpy(wl.labels.astype(np.uint8)).to(dev)
+    ekap = precision.expected_kappa(wl.H.astype(np.complex64), wl.sigma2, L, sample=64)
+    fmt_e, ub = precision.choose_format(K, ekap)
+    kap = torch.empty((B,), dtype=torch.float32, device=dev)
+    out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
+           torch.empty((B,), dtype=torch.int32, device=dev))
+    fp.detect(H, Y, s2, q, it, L, fmt_e, variant=2, ctx=ctx, out=out, stream=stream, kappa=kap)
+    torch.cuda.synchronize()
+    ber_uniform = ber_of(out[1], tx, q)
+    fmts = precision.formats_per_channel(kap, K, allowed=("fp16", "fp32"))
+    groups = {f: int((fmts == f).sum()) for f in ("fp16", "fp32")}
+    idx = {f: torch.from_numpy(np.nonzero(fmts == f)[0].astype(np.int32)).to(dev) for f in groups if groups[f]}
+
+    def adaptive():
+        for f, ix in idx.items():
+            fp.detect(H, Y, s2, q, it, L, f, variant=2, ctx=ctx, out=out, stream=stream, chan_idx=ix)
+
+    uniform = lambda: fp.detect(H, Y, s2, q, it, L, fmt_e, variant=2, ctx=ctx, out=out, stream=stream)
+    tu, ta = [], []
+    for _ in range(rounds):
+        tu.append(timed(uniform))
+        ta.append(timed(adaptive))
+    tu, ta = np.concatenate(tu), np.concatenate(ta)
+    adaptive()
+    torch.cuda.synchronize()
+    ber_adapt = ber_of(out[1], tx, q)
+    log(f"c3 L=8 I=16: E[kappa] {ekap:.2f} -> {fmt_e} for all channels, p50 {np.median(tu):.4f} ms, BER {ber_uniform:.4e}; "
+        f"per channel {groups}, p50 {np.median(ta):.4f} ms, BER {ber_adapt:.4e}")
+    res["c3"] = {"workload": "c3 shape, zeta 0, 0.125, ..., 0.875 in eight equal groups", "L": L, "variant": 2, "iters": it, "B": B,
+                 "expected_kappa": round(ekap, 3), "heuristic_format": fmt_e,
+                 "per_channel_formats": groups, "uniform_p50_ms": round(float(np.median(tu)), 5),
+                 "adaptive_p50_ms": round(float(np.median(ta)), 5),
+                 "speedup": round(float(np.median(tu) / np.median(ta)), 3),
+                 "ber_uniform": ber_uniform, "ber_adaptive": ber_adapt}
+    print(json.dumps(res))
+
+
 def serve_bench(args, n_pool=24, n_requests=400, seed=5):
     """Requests with (Nbs, K) uniform over the built pairs with K <= Nbs/2,
     1..1200 channels of 14 received vectors, correlation U[0, 0.9], SNR
@@ -239,6 +399,9 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: Poisson arrivals of mixed-shape requests through the continuous-batching "
                          "loop; p50/p99 request latency and throughput at several offered loads")
+    ap.add_argument("--kappa", action="store_true",
+                    help="per-channel precision selection from kappa estimated on the device: its cost at c2, "
+                         "its accuracy, and per-channel formats at c3 against the heuristic's single format")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs of a --profile run (FETCH_SIZE, then WRITE_SIZE) "
                          "into the HBM-traffic record bench.py reports, then exit")
@@ -250,6 +413,9 @@ def main():
 
     if args.serve and args.gpus == 1:
         serve_bench(args)
+        return
+    if args.kappa and args.gpus == 1:
+        kappa_bench(args)
         return
 
     if args.gpus != 1:

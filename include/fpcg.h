@@ -177,7 +177,8 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream,
  *     kappa) are written; indices outside [0, B) are skipped.  n_idx is
  *     ignored when chan_idx is NULL (all B channels).
  *   kappa: NULL, or a device array of B floats: for each detected channel,
- *     the largest over its received vectors of lambda_max(T) / lambda_min(T),
+ *     the largest over its first min(R, 4) received vectors of
+ *     lambda_max(T) / lambda_min(T),
  *     T the Lanczos tridiagonal of the CG coefficients of the first solve
  *     (T[0][0] = 1/alpha_1, T[i][i] = 1/alpha_{i+1} + beta_i/alpha_i,
  *     T[i-1][i]^2 = beta_i/alpha_i^2, from the first min(iters, 32) steps
@@ -185,7 +186,7 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream,
  *     the iteration matrix (A without preconditioner, M_d A or A_bar with
  *     it) from below; NaN when no step was taken (iters = 0, breakdown in
  *     the first step).  Needs a stream-ordered workspace of
- *     n * R * iters * 8 bytes (FPCG_E_NOMEM if it cannot be had).
+ *     n * min(R, 4) * iters * 8 bytes (FPCG_E_NOMEM if it cannot be had).
  *   Always one workgroup per channel (the launch form setting is not used).
  *   Errors as fpcg_detect, plus FPCG_E_INVAL for n_idx outside [0, 2^31). */
 fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,

@@ -38,6 +38,9 @@
 
 namespace fpcg {
 
+// received-vector columns whose CG coefficients feed the kappa estimate
+constexpr int KAPPA_COLS = 4;
+
 struct FusedParams {
     const void* H;
     const void* Y;
@@ -53,7 +56,8 @@ struct FusedParams {
     int32_t m, bits;
     // optional: the launch's channels as indices into the batch (NULL: all B
     // in order; grid x = their count), and a record of the first solve's CG
-    // coefficients, [launch position][column][iteration][alpha, beta] (NULL: none)
+    // coefficients of the first min(R, KAPPA_COLS) received-vector columns,
+    // [launch position][column][iteration][alpha, beta] (NULL: none)
     const int32_t* chan_idx;
     float* ab_hist;
 };
@@ -1414,9 +1418,10 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 }
             }
             rho_cur = rho_new;
-            if (MODE == MODE_FULL && P.ab_hist && pass == 0 && g == 0 && wave == 0 && colv) {
-                // one lane per received-vector column records alpha_i, beta_i
-                float* h = P.ab_hist + (((int64_t)blockIdx.x * R + col) * P.iters + (it - 1)) * 2;
+            if (MODE == MODE_FULL && P.ab_hist && pass == 0 && g == 0 && wave == 0 && colv && col < KAPPA_COLS) {
+                // one lane per recorded received-vector column writes alpha_i, beta_i
+                const int nrec = R < KAPPA_COLS ? R : KAPPA_COLS;
+                float* h = P.ab_hist + (((int64_t)blockIdx.x * nrec + col) * P.iters + (it - 1)) * 2;
                 h[0] = (float)alpha_rec;
                 h[1] = (float)beta_rec;
             }

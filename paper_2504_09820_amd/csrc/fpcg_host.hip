@@ -318,6 +318,14 @@ fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out) {
     fpcg_ctx* c = new fpcg_ctx();
     c->device = device;
     c->budget = hbm_budget ? hbm_budget : (size_t)(0.8 * (double)free_b);
+    // the coefficient record of fpcg_detect_ex comes from the device's default
+    // stream-ordered pool: keep freed blocks there for the next call instead of
+    // returning them to the driver at every synchronisation
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
     (void)table();
     *out = c;
     return FPCG_OK;
@@ -374,7 +382,7 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, 
     LaunchExtra ex;
     ex.chan_idx = chan_idx;
     ex.n = n;
-    const size_t hist_bytes = kappa && iters > 0 ? (size_t)n * R * iters * 2 * sizeof(float) : 0;
+    const size_t hist_bytes = kappa && iters > 0 ? (size_t)n * std::min(R, KAPPA_COLS) * iters * 2 * sizeof(float) : 0;
     if (hist_bytes) {
         void* h = nullptr;
         if (hipMallocAsync(&h, hist_bytes, s) != hipSuccess || !h)

@@ -54,7 +54,8 @@ def _oracle_kappa(wl, io, qam, iters, L, name, variant=0, accum="exact", H=None,
     Yn = (wl.Y if Y is None else Y).astype(io).astype(np.complex128)
     co = []
     D.detect(Hn, Yn, wl.sigma2, qam, iters, L, oracle_sched(name, variant=variant, accum=accum), coeffs=co)
-    return D.lanczos_kappa(co) if co else np.full(Hn.shape[0], np.nan)
+    # the device estimate uses the first four received vectors
+    return D.lanczos_kappa(co, R_valid=min(Yn.shape[2], 4)) if co else np.full(Hn.shape[0], np.nan)
 
 
 def _spectrum_kappa(wl, io, L):
@@ -68,8 +69,8 @@ def _spectrum_kappa(wl, io, L):
     return ev[:, -1] / ev[:, 0]
 
 
-# bisection of the extreme Ritz values: 16 halvings of the upper bracket and
-# 18 of the lower one's logarithm, on coefficients recorded in fp32
+# bisection of the extreme Ritz values: 14 halvings of the upper bracket and
+# 16 of the lower one's logarithm, on coefficients recorded in fp32
 RTOL = 2e-3
 
 
