@@ -399,6 +399,7 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: Poisson arrivals of mixed-shape requests through the continuous-batching "
                          "loop; p50/p99 request latency and throughput at several offered loads")
+    ap.add_argument("--kappa-profile", action="store_true", help="with --profile: also the launches with kappa output")
     ap.add_argument("--kappa", action="store_true",
                     help="per-channel precision selection from kappa estimated on the device: its cost at c2, "
                          "its accuracy, and per-channel formats at c3 against the heuristic's single format")
@@ -484,6 +485,12 @@ def main():
         cd = cands[0]
         it = args.iters or 11
         wall, per = run(cd["sched"], it, cd["L"], variant, args.steps, args.warmup, idle=IDLE_S)
+        if args.kappa_profile:                       # the same launches with the kappa estimate
+            kap = torch.empty((B,), dtype=torch.float32, device=dev)
+            for _ in range(args.steps):
+                fp.detect(H, Y, s2, q, it, cd["L"], cd["sched"], variant=variant, ctx=ctx, out=(xo, lo, fo),
+                          stream=stream, kappa=kap)
+            torch.cuda.synchronize()
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # a plain copy of known size, to scale
         b = torch.empty_like(a)                                     # the HBM byte counters
         for _ in range(3):
