@@ -17,6 +17,11 @@
  *     Y is (B, Nbs, R): R received vectors per channel sharing that H.
  *     xhat is (B, K, R) in the same element type as H and Y; labels is
  *     (B, K, R) uint8; flags is (B) uint32; sigma2 is (B) double.
+ *   - sigma2[c] >= 0 is added on the Gram's diagonal (A = H^H H + sigma2 I,
+ *     the LMMSE system of eq. inversion); sigma2[c] = 0 gives the
+ *     zero-forcing system A = H^H H of the same equation, which is positive
+ *     definite only when H has full column rank (K <= Nbs): a singular block
+ *     or a breakdown is flagged, never a call error.
  *   - Device pointers are memory of the device the context was created on.
  *     The caller allocates and frees them; the library never frees or keeps
  *     caller memory beyond the asynchronous work it enqueued.

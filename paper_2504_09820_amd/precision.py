@@ -101,3 +101,36 @@ def detect_adaptive(H, Y, sigma2, qam: int, iters: int, L: int, formats, variant
                chan_idx=idx)
         groups[name] = int(sel.size)
     return out[0], out[1], out[2], groups
+
+
+# ---------------------------------------------------------------- block size
+def cg_iterations(kappa: float, eps: float = 1e-3) -> int:
+    """Steps after which the classical CG error bound 2 ((sqrt(k) - 1) /
+    (sqrt(k) + 1))^i (A-norm, relative) drops below eps."""
+    if not kappa >= 1.0:
+        raise ValueError("kappa must be >= 1")
+    if kappa == 1.0:
+        return 1
+    s = np.sqrt(kappa)
+    return int(np.ceil(np.log(2.0 / eps) / np.log((s + 1.0) / (s - 1.0))))
+
+
+def bj_setup_over_iteration(K: int, L: int) -> float:
+    """C_BJ / C^it of Remark 4 with its scalings made exact as in Remark 5:
+    N L^2 multiplications for the block inverses against N^2 for the
+    iteration's A p (N = K): L^2 / K (K = 32, L = 8 gives 2 iterations)."""
+    return (L * L) / K if L else 0.0
+
+
+def choose_block_size(K: int, kappas: dict, eps: float = 1e-3, setup_cost=bj_setup_over_iteration):
+    """Block size by the break-even rule of Remark 4: with k(L) the iterations
+    the CG bound needs on the system preconditioned with L x L blocks (kappa
+    from `kappas`, {L: kappa}, L = 0 for none), preconditioning with L pays
+    when k(0) - k(L) > C_BJ(L) / C^it.  Returns (L, {L: total cost in
+    iterations}) with the smallest total (the smaller L on a tie).
+    `setup_cost(K, L)` gives C_BJ / C^it; the default is the paper's
+    multiplication count, a measured ratio of the device's setup and
+    iteration times can be passed instead."""
+    total = {L: setup_cost(K, L) + cg_iterations(k, eps) for L, k in kappas.items()}
+    best = min(sorted(total), key=lambda L: total[L])
+    return best, total
