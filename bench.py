@@ -286,6 +286,78 @@ def kappa_bench(args, steps=30, rounds=3):
     print(json.dumps(res))
 
 
+def robust_bench(args, B=4096, snr_db=26.7):
+    """Robustness workloads of Sec. V at c2's shape (Nbs = 128, K = 32, 64-QAM,
+    14 received vectors), at the SNR of c2's BER-1e-3 operating point: bit error
+    rates of the converged LMMSE solve (FP64, I = 96), FP64 CG (I = 15) and the
+    timed FP-BJ-CG schedule (fp16, L = 4, symmetric form, I = 11, and I = 16)
+    with perfect CSI, imperfect CSI at eps = 20 and 25 dB, and the
+    geometry-based channel; and a Gauss-Markov sequence (zeta = 0.8, f_d =
+    1 kHz, eight steps): the heuristic's format per step from E{kappa}, the
+    share of channels whose per-channel format (kappa estimated on the device)
+    changes between steps, and the BER per step with the format chosen at the
+    first step (I = 24) beside the converged LMMSE BER.  One JSON line."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+    from paper_2504_09820_amd import precision
+
+    dev = torch.device("cuda:0")
+    ctx = fp.Context(0)
+    Nbs, K, R, q = 128, 32, 14, 64
+
+    def ber(wl, sched, it, L, v):
+        H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+        Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+        s2 = torch.from_numpy(wl.sigma2).to(dev)
+        _, lab, _ = fp.detect(H, Y, s2, q, it, L, sched, variant=v, ctx=ctx)
+        return ber_of(lab, torch.from_numpy(wl.labels.astype(np.uint8)).to(dev), q)
+
+    res = {"mode": "robustness", "shape": f"Nbs={Nbs} K={K} R={R} 64-QAM B={B} SNR={snr_db} dB"}
+    base = W.draw(B, Nbs, K, R, q, snr_db, 0.5, 0.5, seed=2504_09820 * 10 + 61)
+    cases = {"perfect CSI (zeta 0.5)": base,
+             "imperfect CSI, eps 25 dB": W.imperfect_csi(base, 25.0, seed=62),
+             "imperfect CSI, eps 20 dB": W.imperfect_csi(base, 20.0, seed=63),
+             "geometry, 5 paths, mu 1": W.geometry(B, Nbs, K, R, q, snr_db, seed=64)}
+    rows = {}
+    for name, wl in cases.items():
+        r = {"lmmse_fp64": ber(wl, "fp64", 96, 0, 0), "fp64_cg_I15": ber(wl, "fp64", 15, 0, 0),
+             "fp_bj_cg_fp16_L4_I11": ber(wl, "fp16", 11, 4, 2), "fp_bj_cg_fp16_L4_I16": ber(wl, "fp16", 16, 4, 2)}
+        log(f"{name}: BER LMMSE {r['lmmse_fp64']:.3e}, FP64 CG {r['fp64_cg_I15']:.3e}, FP-BJ-CG fp16 "
+            f"{r['fp_bj_cg_fp16_L4_I11']:.3e} (I=11) {r['fp_bj_cg_fp16_L4_I16']:.3e} (I=16)")
+        rows[name] = r
+    res["ber"] = rows
+    # time variation
+    steps = W.gauss_markov(B, Nbs, K, R, q, snr_db, 0.8, 0.8, 8, 1000.0, seed=2504_09820 * 10 + 70)
+    fmt0 = None
+    seq = []
+    prev = None
+    for i, wl in enumerate(steps):
+        ek = precision.expected_kappa(wl.H.astype(np.complex64), wl.sigma2, 4, sample=64)
+        f, _ = precision.choose_format(K, ek)
+        fmt0 = fmt0 or f
+        H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+        Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+        s2 = torch.from_numpy(wl.sigma2).to(dev)
+        kap = torch.empty((B,), dtype=torch.float32, device=dev)
+        _, lab, _ = fp.detect(H, Y, s2, q, 24, 4, fmt0, variant=2, ctx=ctx, kappa=kap)
+        b = ber_of(lab, torch.from_numpy(wl.labels.astype(np.uint8)).to(dev), q)
+        b_lmmse = ber(wl, "fp64", 96, 0, 0)
+        per = precision.formats_per_channel(kap, K, allowed=("fp16", "fp32"))
+        changed = None if prev is None else float(np.mean(per != prev))
+        prev = per
+        seq.append({"step": i, "expected_kappa": round(ek, 3), "heuristic": f, "ber_with_step0_format": b,
+                    "ber_lmmse": b_lmmse,
+                    "per_channel_fp16_share": round(float(np.mean(per == "fp16")), 4),
+                    "per_channel_changed": changed})
+        log(f"GM step {i}: E[kappa] {ek:.2f} -> {f}; BER with {fmt0} (I=24): {b:.3e}, LMMSE {b_lmmse:.3e}; per-channel fp16 share "
+            f"{np.mean(per == 'fp16'):.3f}, changed {changed}")
+    res["gauss_markov"] = {"zeta": 0.8, "fd_hz": 1000.0, "tau_s": 1.0 / 14000.0, "L": 4, "iters": 24,
+                           "format_step0": fmt0, "steps": seq}
+    print(json.dumps(res))
+
+
 def serve_bench(args, n_pool=24, n_requests=400, seed=5):
     """Requests with (Nbs, K) uniform over the built pairs with K <= Nbs/2,
     1..1200 channels of 14 received vectors, correlation U[0, 0.9], SNR
@@ -399,6 +471,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: Poisson arrivals of mixed-shape requests through the continuous-batching "
                          "loop; p50/p99 request latency and throughput at several offered loads")
+    ap.add_argument("--robust", action="store_true",
+                    help="robustness workloads: BER with imperfect CSI, geometry channels, Gauss-Markov variation")
     ap.add_argument("--kappa-profile", action="store_true", help="with --profile: also the launches with kappa output")
     ap.add_argument("--kappa", action="store_true",
                     help="per-channel precision selection from kappa estimated on the device: its cost at c2, "
@@ -417,6 +491,9 @@ def main():
         return
     if args.kappa and args.gpus == 1:
         kappa_bench(args)
+        return
+    if args.robust and args.gpus == 1:
+        robust_bench(args)
         return
 
     if args.gpus != 1:

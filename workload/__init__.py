@@ -35,6 +35,9 @@ __all__ = [
     "Workload",
     "draw",
     "sigma2_from_snr_db",
+    "imperfect_csi",
+    "gauss_markov",
+    "geometry",
     "CONFIGS",
 ]
 
@@ -101,6 +104,7 @@ class Workload:
     sigma2: np.ndarray     # (B,) float64
     q: int
     snr_db: np.ndarray     # (B,) float64
+    H_true: np.ndarray = None   # the channel Y was drawn with, when H is only an estimate of it
 
     @property
     def shape(self):
@@ -149,6 +153,74 @@ def draw(
     if not noiseless:
         nz = (rng.standard_normal((B, Nbs, R)) + 1j * rng.standard_normal((B, Nbs, R)))
         Y = Y + nz * np.sqrt(sigma2 / 2.0)[:, None, None]
+    return Workload(H=H, Y=Y, labels=labels, X=X, sigma2=sigma2, q=q, snr_db=snr)
+
+
+# ---------------------------------------------------------------- robustness workloads
+# (Sec. V, robustness to imperfect CSI, geometry-based and time-varying channels)
+
+def imperfect_csi(wl: Workload, eps_db: float, seed: int = 0) -> Workload:
+    """The workload seen through a channel estimate H_hat = H + dH: dH has
+    i.i.d. CN(0, P / eps) entries, P the mean entry power of H and eps the
+    channel-to-error power ratio (10^(eps_db/10)).  Y keeps the true channel
+    (kept in ``H_true``); H becomes the estimate the detector uses."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = float(np.mean(np.abs(wl.H) ** 2))
+    var = P / 10.0 ** (eps_db / 10.0)
+    dH = (rng.standard_normal(wl.H.shape) + 1j * rng.standard_normal(wl.H.shape)) * math.sqrt(var / 2.0)
+    return dataclasses.replace(wl, H=wl.H + dH, H_true=wl.H)
+
+
+def gauss_markov(B: int, Nbs: int, K: int, R: int, q: int, snr_db: float, zeta_r: float, zeta_t: float,
+                 steps: int, fd_hz: float, tau_s: float = 1.0 / 14000.0, seed: int = 0,
+                 normalization: str = "paper") -> list:
+    """First-order Gauss-Markov evolution H_i = rho H_{i-1} + sqrt(1 - rho^2) W_i
+    with rho = J0(2 pi f_d tau) and W_i independent draws of the same Kronecker
+    covariance; each step carries new symbols and noise.  tau defaults to one
+    OFDM symbol at 15 kHz subcarrier spacing (a reading: the paper does not
+    give it).  Returns the list of the steps' workloads."""
+    from scipy.special import j0
+
+    rho = float(j0(2.0 * math.pi * fd_hz * tau_s))
+    out = [draw(B, Nbs, K, R, q, snr_db, zeta_r, zeta_t, seed=seed, normalization=normalization)]
+    for i in range(1, steps):
+        w = draw(B, Nbs, K, R, q, snr_db, zeta_r, zeta_t, seed=seed + 7919 * i, normalization=normalization)
+        H = rho * out[-1].H + math.sqrt(max(0.0, 1.0 - rho * rho)) * w.H
+        rng = np.random.Generator(np.random.PCG64(seed + 104729 * i))
+        Y = np.matmul(H, w.X)
+        nz = rng.standard_normal(Y.shape) + 1j * rng.standard_normal(Y.shape)
+        Y = Y + nz * np.sqrt(w.sigma2 / 2.0)[:, None, None]
+        out.append(dataclasses.replace(w, H=H, Y=Y))
+    return out
+
+
+def geometry(B: int, Nbs: int, K: int, R: int, q: int, snr_db, paths: int = 5, mu: float = 1.0, seed: int = 0) -> Workload:
+    """Geometry-based multipath channel for single-antenna users: column k is
+    sum_i alpha_i a(phi_i) over `paths` paths, the first (line of sight) with
+    alpha ~ CN(0, 1), the others CN(0, 10^-mu), angles of arrival U(-pi, pi)
+    at a half-wavelength uniform linear array, a(phi) = [e^{j pi n sin phi}] /
+    sqrt(Nbs).  Readings: the base-station response is the array's column
+    (the paper's a_t a_r^H written as the M x N_k matrix a_r a_t^H, a_t = 1 for
+    one antenna); columns are scaled to E||h_k||^2 = 1 so the SNR reading of
+    draw() applies (the scale does not change x_hat)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gain = np.sqrt(np.concatenate([[1.0], np.full(paths - 1, 10.0 ** (-mu))]))
+    norm = 1.0 / math.sqrt(float(np.sum(gain ** 2)))
+    n = np.arange(Nbs)
+    H = np.zeros((B, Nbs, K), dtype=np.complex128)
+    for p in range(paths):
+        phi = rng.uniform(-math.pi, math.pi, size=(B, 1, K))
+        a = np.exp(1j * math.pi * n[None, :, None] * np.sin(phi)) / math.sqrt(Nbs)
+        alpha = (rng.standard_normal((B, 1, K)) + 1j * rng.standard_normal((B, 1, K))) * (gain[p] / math.sqrt(2.0))
+        H += alpha * a
+    H *= norm                                         # E||h_k||^2 = 1
+    labels = rng.integers(0, q, size=(B, K, R), dtype=np.int64)
+    X = qam_points(labels, q)
+    snr = np.broadcast_to(np.asarray(snr_db, dtype=np.float64), (B,)).copy()
+    sigma2 = np.array([sigma2_from_snr_db(s, Nbs, "paper") for s in snr])
+    Y = np.matmul(H, X)
+    nz = rng.standard_normal(Y.shape) + 1j * rng.standard_normal(Y.shape)
+    Y = Y + nz * np.sqrt(sigma2 / 2.0)[:, None, None]
     return Workload(H=H, Y=Y, labels=labels, X=X, sigma2=sigma2, q=q, snr_db=snr)
 
 
