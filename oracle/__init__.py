@@ -12,6 +12,10 @@ Contents
                (FP-CG), eq. pre_BJ and Alg. 3 (FP-BJ-CG) step by step, the
                emulated precision schedule, FP64 residual refresh, FP64
                iterative refinement, the QAM slicer and bit-error counting.
+  demap     -- soft output after detection: the effective gain of each
+               user from eq. pre_BJ's block inverses and max-log LLRs over the
+               Gray QAM points (readings in its header), with the exact LLRs
+               of the same model for the pins.
   theory    -- unit roundoffs, gamma_n (eq. gamma), the attainable-accuracy
                bounds of Thm 2 / Thm 4, the precision heuristic (eq. heuristic,
                eq. heuristic_bj), the Gram-entry moments of App. B and the
