@@ -286,6 +286,114 @@ def kappa_bench(args, steps=30, rounds=3):
     print(json.dumps(res))
 
 
+def soft_bench(args, steps=30, rounds=3):
+    """Soft output (max-log LLRs for a channel decoder).  c2 with the timed
+    schedule (fp16, L = 4, symmetric form, I = 11): the detection with the
+    gain output against the plain detection, and the demapper on its own
+    (HIP events on the launch stream; algorithmic bytes: the estimate read,
+    the gains read, the LLRs written).  Then LLR quality in the paper's coded
+    setting (Nbs = 256, K = 32, correlation 0.8, 16-QAM, L = 8, I = 10) over
+    SNR: bit error rate of the LLR signs and the bit-wise mutual information
+    estimated from the LLRs, 1 - E log2(1 + exp(-(1 - 2b) LLR)), for the
+    fp16 FP-BJ-CG schedule and for a converged FP64 solve (the LMMSE
+    estimate) with the same gains.  One JSON line."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = fp.Context(0)
+    res = {"mode": "soft"}
+
+    def timed(fn, n=steps):
+        torch.cuda.synchronize()
+        time.sleep(IDLE_S)
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+
+    c = W.CONFIGS["c2"]
+    B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
+    wl = W.draw(B, Nbs, K, R, q, c["snr_db"], c["zeta"], c["zeta"], seed=2504_09820 * 10 + 2,
+                normalization=c["normalization"])
+    H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    s2 = torch.from_numpy(wl.sigma2).to(dev)
+    out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
+           torch.empty((B,), dtype=torch.int32, device=dev))
+    gain = torch.empty((B, K), dtype=torch.float32, device=dev)
+    nb = int(math.log2(q))
+    llr = torch.empty((B, K, R, nb), dtype=torch.float32, device=dev)
+    plain = lambda: fp.detect(H, Y, s2, q, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=stream)
+    withg = lambda: fp.detect(H, Y, s2, q, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=stream, gain=gain)
+    demap = lambda: fp.demap_maxlog(out[0], gain, q, out=llr, stream=stream)
+
+    def soft():
+        withg()
+        demap()
+
+    tp, tg, td, ts = [], [], [], []
+    for _ in range(rounds):
+        tp.append(timed(plain))
+        tg.append(timed(withg))
+        td.append(timed(demap, 3 * steps))
+        ts.append(timed(soft))
+    tp, tg, td, ts = (np.concatenate(t) for t in (tp, tg, td, ts))
+    n_sym = B * K * R
+    dbytes = n_sym * (8 + 4 * nb) + B * K * 4
+    ach = dbytes / (float(np.mean(td)) * 1e-3) / 1e9
+    log(f"c2 fp16 L=4 I=11: detection p50 {np.median(tp):.4f} ms, with gains {np.median(tg):.4f} ms, "
+        f"demap p50 {np.median(td):.4f} ms ({ach:.0f} GB/s mean), detection + demap {np.median(ts):.4f} ms")
+    res["c2"] = {"schedule": "fp16", "L": 4, "variant": 2, "iters": 11, "B": B, "qam": q,
+                 "detect_p50_ms": round(float(np.median(tp)), 5),
+                 "detect_with_gain_p50_ms": round(float(np.median(tg)), 5),
+                 "demap_p50_ms": round(float(np.median(td)), 5), "demap_mean_ms": round(float(np.mean(td)), 5),
+                 "soft_path_p50_ms": round(float(np.median(ts)), 5),
+                 "soft_detections_per_s": round(B * R / (float(np.median(ts)) * 1e-3), 1),
+                 "demap_roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": dbytes}}
+    del H, Y, s2, out, gain, llr
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- LLR quality, the coded setting
+    Bq, Nq, Kq, Rq, qq = 2048, 256, 32, 14, 16
+    nbq = 4
+    curve = []
+    for snr in (0.0, 2.0, 4.0, 6.0, 8.0, 10.0):
+        w = W.draw(Bq, Nq, Kq, Rq, qq, snr, 0.8, 0.8, seed=2504_09820 * 10 + 80 + int(snr))
+        Ht = torch.from_numpy(w.H.astype(np.complex64)).to(dev)
+        Yt = torch.from_numpy(w.Y.astype(np.complex64)).to(dev)
+        st = torch.from_numpy(w.sigma2).to(dev)
+        lab = torch.from_numpy(w.labels.astype(np.int64)).to(dev)
+        bits = torch.stack([(lab >> (nbq - 1 - t)) & 1 for t in range(nbq)], dim=-1).to(torch.float32)
+        row = {"snr_db": snr}
+        for name, sched, iters, io in (("lmmse_fp64", "fp64", 64, torch.complex128), ("fp_bj_cg_fp16_I10", "fp16", 10, torch.complex64)):
+            g = torch.empty((Bq, Kq), dtype=torch.float32, device=dev)
+            x, _, _ = fp.detect(Ht.to(io), Yt.to(io), st, qq, iters, 8, sched, variant=2, ctx=ctx, gain=g)
+            L_ = fp.demap_maxlog(x, g, qq)
+            sgn = 1.0 - 2.0 * bits
+            mi = 1.0 - float(torch.mean(torch.log2(1.0 + torch.exp(torch.clamp(-sgn * L_, max=80.0)))).item())
+            ber = float(((L_ < 0).to(torch.float32) != bits).to(torch.float32).mean().item())
+            row[name] = {"ber_llr_sign": ber, "mutual_information": round(mi, 5)}
+        log(f"coded setting {snr:4.1f} dB: LMMSE BER {row['lmmse_fp64']['ber_llr_sign']:.4e} MI "
+            f"{row['lmmse_fp64']['mutual_information']:.4f} | fp16 FP-BJ-CG BER {row['fp_bj_cg_fp16_I10']['ber_llr_sign']:.4e} "
+            f"MI {row['fp_bj_cg_fp16_I10']['mutual_information']:.4f}")
+        curve.append(row)
+        del Ht, Yt, st, lab, bits
+    res["coded_setting"] = {"shape": f"Nbs={Nq} K={Kq} R={Rq} 16-QAM B={Bq} correlation 0.8", "L": 8, "variant": 2,
+                            "curve": curve}
+    print(json.dumps(res))
+
+
 def robust_bench(args, B=4096, snr_db=26.7):
     """Robustness workloads of Sec. V at c2's shape (Nbs = 128, K = 32, 64-QAM,
     14 received vectors), at the SNR of c2's BER-1e-3 operating point: bit error
@@ -473,6 +581,8 @@ def main():
                          "loop; p50/p99 request latency and throughput at several offered loads")
     ap.add_argument("--robust", action="store_true",
                     help="robustness workloads: BER with imperfect CSI, geometry channels, Gauss-Markov variation")
+    ap.add_argument("--soft", action="store_true",
+                    help="soft output: gain output and max-log demapper timed at c2, LLR quality over SNR")
     ap.add_argument("--kappa-profile", action="store_true", help="with --profile: also the launches with kappa output")
     ap.add_argument("--kappa", action="store_true",
                     help="per-channel precision selection from kappa estimated on the device: its cost at c2, "
@@ -494,6 +604,9 @@ def main():
         return
     if args.robust and args.gpus == 1:
         robust_bench(args)
+        return
+    if args.soft and args.gpus == 1:
+        soft_bench(args)
         return
 
     if args.gpus != 1:

@@ -192,6 +192,13 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream,
  *     it) from below; NaN when no step was taken (iters = 0, breakdown in
  *     the first step).  Needs a stream-ordered workspace of
  *     n * min(R, 4) * iters * 8 bytes (FPCG_E_NOMEM if it cannot be had).
+ *   gain: NULL, or a device array of B * K floats, [channel][user]: for each
+ *     detected channel the effective gain of each user's estimate,
+ *     mu_k = 1 - sigma^2 (M)_kk, M the block-Jacobi inverse of eq. pre_BJ
+ *     (the inverses of A's L x L diagonal blocks, computed in u_W; the
+ *     diagonal fallback for a block that is not positive definite) and
+ *     diag(A)^{-1} when L = 0.  With L = K it is the exact LMMSE gain
+ *     (A^{-1} H^H H)_kk.  The input of fpcg_demap_maxlog.
  *   Always one workgroup per channel (the launch form setting is not used).
  *   Errors as fpcg_detect, plus FPCG_E_INVAL for n_idx outside [0, 2^31). */
 fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
@@ -200,7 +207,28 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
                            int32_t qam_order, int32_t iters, int32_t block_L,
                            const fpcg_schedule* sched,
                            void* xhat, uint8_t* labels, uint32_t* flags,
-                           const int32_t* chan_idx, int64_t n_idx, float* kappa);
+                           const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain);
+
+/* Soft output for a channel decoder (Sec. V evaluates the detector in a coded
+ * link, Fig. coding): max-log LLRs of each estimated symbol.  The model of
+ * the LMMSE estimate with unit-energy symbols is x_hat = mu s + e, e of
+ * variance nu^2 = mu (1 - mu); for each label bit
+ *   LLR = (min_{s: bit = 1} |x_hat - mu s|^2 - min_{s: bit = 0} |x_hat - mu s|^2) / nu^2,
+ * positive when the bit is more likely 0, over the unit-energy Gray square
+ * QAM of fpcg_slice.  mu is clamped to [0, 1]; where nu^2 = 0 (mu = 0: no
+ * signal; mu = 1: zero-forcing) an LLR is 0 where the distances tie and
+ * +-infinity otherwise; NaN in mu, or NaN or infinity in either component
+ * of x, makes all of that symbol's LLRs NaN.
+ *   n >= 0 symbols x: complex64 (x_c64 != 0, computed in FP32) or complex128
+ *     (computed in FP64), device.
+ *   gain: device floats, symbol i uses gain[i / R] (R >= 1): the detector's
+ *     [channel][user] gains with x_hat laid out (B, K, R).
+ *   llr: device, 16-byte aligned, n * log2(Q) floats, [symbol][bit] with
+ *     the label's most significant bit first (the I axis's bits, then Q's).
+ *   Asynchronous on `stream`; FPCG_E_INVAL for bad sizes, Q, NULL pointers
+ *   or alignment. */
+fpcg_status fpcg_demap_maxlog(void* stream, int64_t n, int32_t R, const void* x, int32_t x_c64,
+                              const float* gain, int32_t qam_order, float* llr);
 
 /* QAM slicer on its own (the detector's epilogue): nearest unit-energy
  * square-QAM point per complex value, decided in FP32 (x_c64 != 0) or FP64.

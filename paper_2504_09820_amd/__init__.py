@@ -17,7 +17,7 @@ from typing import Optional
 
 __all__ = [
     "FMT", "FLAGS", "Schedule", "schedule", "Context", "FpcgError", "lib", "library_path",
-    "detect", "check", "slice_qam", "round_operand", "select_precision", "Server",
+    "detect", "check", "slice_qam", "demap_maxlog", "round_operand", "select_precision", "Server",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -98,8 +98,10 @@ def lib():
     L.fpcg_detect.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule), vp, vp, vp]
     L.fpcg_detect.restype = st
     L.fpcg_detect_ex.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule),
-                                 vp, vp, vp, vp, i64, vp]
+                                 vp, vp, vp, vp, i64, vp, vp]
     L.fpcg_detect_ex.restype = st
+    L.fpcg_demap_maxlog.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp]
+    L.fpcg_demap_maxlog.restype = st
     L.fpcg_slice.argtypes = [vp, i64, vp, i32, i32, vp]
     L.fpcg_slice.restype = st
     L.fpcg_round.argtypes = [vp, i64, vp, i32, ctypes.c_float, vp]
@@ -201,7 +203,7 @@ def _stream_handle(stream, device):
 
 def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Schedule" = "fp64",
            refresh_every: int = 0, refine_steps: int = 0, variant: int = 0,
-           ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None):
+           ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None, gain=None):
     """Run the detector on device tensors.
 
     H (B, Nbs, K) and Y (B, Nbs, R): complex64 or complex128 CUDA tensors,
@@ -209,7 +211,8 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     (xhat (B, K, R) like H, labels (B, K, R) uint8, flags (B,) int32 bits).
     chan_idx (int32 CUDA tensor) restricts the launch to those channels;
     kappa (float32 CUDA tensor of B) receives per-channel condition-number
-    estimates (fpcg_detect_ex).
+    estimates and gain (float32 CUDA tensor (B, K)) each user's effective
+    gain, the input of demap_maxlog (fpcg_detect_ex).
     """
     import torch
 
@@ -238,11 +241,14 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         flags = torch.empty((B,), dtype=torch.int32, device=H.device)
     else:
         xhat, labels, flags = out
-    if chan_idx is not None or kappa is not None:
+    if chan_idx is not None or kappa is not None or gain is not None:
         if chan_idx is not None and (chan_idx.dtype != torch.int32 or not chan_idx.is_cuda):
             raise TypeError("chan_idx must be an int32 CUDA tensor")
         if kappa is not None and (kappa.dtype != torch.float32 or not kappa.is_cuda or kappa.shape != (B,)):
             raise TypeError("kappa must be a float32 CUDA tensor of shape (B,)")
+        if gain is not None and (gain.dtype != torch.float32 or not gain.is_cuda or gain.shape != (B, K)
+                                 or not gain.is_contiguous()):
+            raise TypeError("gain must be a contiguous float32 CUDA tensor of shape (B, K)")
         idx = chan_idx.contiguous() if chan_idx is not None else None
         _check(lib().fpcg_detect_ex(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                                     ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
@@ -252,7 +258,8 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
                                     ctypes.c_void_p(flags.data_ptr()),
                                     ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
                                     idx.numel() if idx is not None else 0,
-                                    ctypes.c_void_p(kappa.data_ptr() if kappa is not None else 0)))
+                                    ctypes.c_void_p(kappa.data_ptr() if kappa is not None else 0),
+                                    ctypes.c_void_p(gain.data_ptr() if gain is not None else 0)))
         return xhat, labels, flags
     _check(lib().fpcg_detect(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                              ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
@@ -272,6 +279,26 @@ def slice_qam(x, qam: int, stream=None):
     _check(lib().fpcg_slice(_stream_handle(stream, x.device), x.numel(), ctypes.c_void_p(x.data_ptr()),
                             1 if x.dtype == torch.complex64 else 0, qam, ctypes.c_void_p(labels.data_ptr())))
     return labels
+
+
+def demap_maxlog(x, gain, qam: int, out=None, stream=None):
+    """Max-log LLRs (fpcg_demap_maxlog) of the estimates x (B, K, R) complex
+    CUDA tensor with the detector's gains (B, K) float32: float32 tensor
+    (B, K, R, log2 qam), most significant label bit first."""
+    import torch
+
+    x = x.contiguous()
+    if x.dim() != 3 or gain.shape != x.shape[:2] or gain.dtype != torch.float32 or not gain.is_cuda:
+        raise TypeError("x must be (B, K, R) and gain a float32 CUDA tensor (B, K)")
+    nb = {4: 2, 16: 4, 64: 6, 256: 8}.get(qam)
+    if nb is None:
+        raise ValueError(f"qam={qam}")
+    gain = gain.contiguous()
+    llr = out if out is not None else torch.empty(tuple(x.shape) + (nb,), dtype=torch.float32, device=x.device)
+    _check(lib().fpcg_demap_maxlog(_stream_handle(stream, x.device), x.numel(), x.shape[2],
+                                   ctypes.c_void_p(x.data_ptr()), 1 if x.dtype == torch.complex64 else 0,
+                                   ctypes.c_void_p(gain.data_ptr()), qam, ctypes.c_void_p(llr.data_ptr())))
+    return llr
 
 
 def round_operand(x, fmt: str, scale: float = 1.0, stream=None):

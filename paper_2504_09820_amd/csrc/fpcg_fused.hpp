@@ -60,6 +60,10 @@ struct FusedParams {
     // [launch position][column][iteration][alpha, beta] (NULL: none)
     const int32_t* chan_idx;
     float* ab_hist;
+    // optional: each user's effective gain mu_k = 1 - sigma^2 (M)_kk, M the
+    // block-Jacobi inverse of the iteration (diag(A)^{-1} without one),
+    // [channel][user] (NULL: none)
+    float* gain;
 };
 
 // Lanes of the symmetric block-Jacobi transform.  Pass 1 (rows) needs rows
@@ -524,6 +528,10 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                                     sDr[row * LB + cc % LB] = ar;
                                     sDi[row * LB + cc % LB] = ai;
                                 }
+                            } else if constexpr (MODE == MODE_FULL) {
+                                // effective gain without a preconditioner: 1 - sigma^2 / a_kk
+                                if (P.gain && cblk == 0 && row == cc && row < K)
+                                    P.gain[ch * K + row] = (float)((Wt)1 - s2w / ar);
                             }
                         }
                     }
@@ -731,6 +739,15 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                 dTi[(cb + r) * LB + i] = ti[r];
             }
             if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
+            if constexpr (MODE == MODE_FULL) {
+                // (M_d)_ii = sum over the rows of |T[r][i]|^2: column i of T is this lane's
+                if (P.gain && cblk == 0 && t < K) {
+                    Wt mii = 0;
+#pragma unroll
+                    for (int r = 0; r < LB; ++r) mii = fma(tr[r], tr[r], fma(ti[r], ti[r], mii));
+                    P.gain[ch * K + t] = (float)((Wt)1 - (Wt)s2 * mii);
+                }
+            }
         }
         bsync();
         if constexpr (!split) {
@@ -841,6 +858,11 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             }
             bsync();
         }
+    }
+
+    if constexpr (LB == 0 && MODE == MODE_FULL && !C::AROW) {   // (AROW: from the Gram epilogue)
+        if (P.gain && cblk == 0)
+            for (int k = tid; k < K; k += NT) P.gain[ch * K + k] = (float)((Wt)1 - (Wt)s2 / sAr[k * LDA + k]);
     }
 
     // element (r, c) of the u_W matrix of the iteration: the Gram (stored whole),

@@ -235,6 +235,7 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
     p.nu = std::sqrt(2.0 * (qam - 1) / 3.0);
     p.chan_idx = indexed ? ex->chan_idx : nullptr;
     p.ab_hist = ex ? ex->ab_hist : nullptr;
+    p.gain = ex ? ex->gain : nullptr;
     const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
     const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
     const int ncb = (R + 15) / 16;
@@ -365,7 +366,7 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int
 fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
                            const void* Y, int32_t io_c64, const double* sigma2, int32_t qam_order, int32_t iters,
                            int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags,
-                           const int32_t* chan_idx, int64_t n_idx, float* kappa) {
+                           const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
     Plan plan;
@@ -382,6 +383,7 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, 
     LaunchExtra ex;
     ex.chan_idx = chan_idx;
     ex.n = n;
+    ex.gain = gain;
     const size_t hist_bytes = kappa && iters > 0 ? (size_t)n * std::min(R, KAPPA_COLS) * iters * 2 * sizeof(float) : 0;
     if (hist_bytes) {
         void* h = nullptr;

@@ -45,6 +45,7 @@ struct LaunchExtra {
     const int32_t* chan_idx = nullptr;
     int64_t n = 0;
     float* ab_hist = nullptr;
+    float* gain = nullptr;
 };
 // one launch in the given form (FPCG_LAUNCH_FUSED or FPCG_LAUNCH_PIPELINED;
 // a launch with extras always runs fused)

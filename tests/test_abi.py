@@ -150,3 +150,20 @@ def test_autotune_validates_before_touching_a_device(fp):
     out = ct.c_int32(-7)
     assert L.fpcg_autotune(None, None, 16, 128, 32, 14, 1, 64, 8, 4, ct.byref(s), 3, ct.byref(out)) == -1
     assert out.value == -7
+
+
+def test_demap_validates_on_the_host(fp):
+    L = fp.lib()
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.addressof(buf)
+    al = (p + 15) & ~15
+    assert L.fpcg_demap_maxlog(None, 0, 1, None, 1, None, 64, None) == 0          # empty: nothing to do
+    assert L.fpcg_demap_maxlog(None, -1, 1, p, 1, p, 64, al) == -1
+    assert L.fpcg_demap_maxlog(None, 4, 0, p, 1, p, 64, al) == -1                 # R < 1
+    for q in (2, 8, 32, 1024):
+        assert L.fpcg_demap_maxlog(None, 4, 1, p, 1, p, q, al) == -1
+    assert L.fpcg_demap_maxlog(None, 4, 1, None, 1, p, 16, al) == -1
+    assert L.fpcg_demap_maxlog(None, 4, 1, p, 1, None, 16, al) == -1
+    assert L.fpcg_demap_maxlog(None, 4, 1, p, 1, p, 16, None) == -1
+    assert L.fpcg_demap_maxlog(None, 4, 1, p, 1, p, 16, al + 4) == -1             # llr not 16-byte aligned
+    assert "aligned" in L.fpcg_last_error().decode()
