@@ -368,7 +368,7 @@ def soft_bench(args, steps=30, rounds=3):
     Bq, Nq, Kq, Rq, qq = 2048, 256, 32, 14, 16
     nbq = 4
     curve = []
-    for snr in (0.0, 2.0, 4.0, 6.0, 8.0, 10.0):
+    for snr in (8.0, 10.0, 12.0, 14.0, 16.0, 18.0, 20.0):
         w = W.draw(Bq, Nq, Kq, Rq, qq, snr, 0.8, 0.8, seed=2504_09820 * 10 + 80 + int(snr))
         Ht = torch.from_numpy(w.H.astype(np.complex64)).to(dev)
         Yt = torch.from_numpy(w.Y.astype(np.complex64)).to(dev)
