@@ -166,3 +166,41 @@ def test_soft_output_after_converged_detection():
     lab = sum(bits[..., t] << (nb - 1 - t) for t in range(nb))
     from oracle import detect as D
     assert np.array_equal(lab, D.slice_qam(ref.xhat / gr[..., None], 64))
+
+
+def test_soft_output_full_size_sampled():
+    """The bench's soft path at its full size (c2: 16384 channels, fp16, L = 4,
+    symmetric form, I = 11, with gains, then the demapper): gains of sampled
+    channels against the oracle's from its own Gram, and the LLRs of those
+    channels against the oracle's demapping of the GPU's estimates and gains."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    c = W.CONFIGS["c2"]
+    B, K, R, q = c["B"], c["K"], c["R"], c["q"]
+    _say(f"case soft output full size c2 B={B}")
+    wl = W.draw(B, c["Nbs"], K, R, q, c["snr_db"], c["zeta"], c["zeta"], seed=78)
+    dev = torch.device("cuda:0")
+    Ht = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Yt = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    st = torch.from_numpy(wl.sigma2).to(dev)
+    g = torch.empty((B, K), dtype=torch.float32, device=dev)
+    x, _, _ = fp.detect(Ht, Yt, st, q, 11, 4, "fp16", variant=2, gain=g)
+    llr = fp.demap_maxlog(x, g, q)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(2).choice(B, 24, replace=False))
+    idx[-1] = B - 1
+    ti = torch.from_numpy(idx).to(dev)
+    xs = x[ti].cpu().numpy().astype(np.complex128)
+    gs = g[ti].cpu().numpy().astype(np.float64)
+    ls = llr[ti].cpu().numpy().astype(np.float64)
+    sub = W.Workload(H=wl.H[idx], Y=wl.Y[idx], labels=wl.labels[idx], X=wl.X[idx], sigma2=wl.sigma2[idx],
+                     q=q, snr_db=wl.snr_db[idx])
+    r1 = oracle_detect(sub, q, 11, 4, "fp16", io=np.complex64, variant=2, accum="exact")
+    r2 = oracle_detect(sub, q, 11, 4, "fp16", io=np.complex64, variant=2, accum="sequential")
+    g1 = DM.effective_gain(r1.A, sub.sigma2, 4, "fp32")
+    spread = np.abs(g1 - DM.effective_gain(r2.A, sub.sigma2, 4, "fp32")).max()
+    assert np.all(np.abs(gs - g1) <= 4 * spread + 64 * 2.0**-24)
+    ref = DM.maxlog_llr(xs, gs[..., None], q)
+    _compare_llr(ls, ref, _llr_tolerance(xs, gs[..., None], q, 2.0**-24), 2.0**-24)
