@@ -35,7 +35,7 @@ __device__ __forceinline__ void axis_llr(T v, T c, T s, float* o) {
     for (int p = 0; p < BA; ++p) { d0[p] = INFINITY; d1[p] = INFINITY; }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const T e = v - c * (T)(2 * j - (M - 1));     // c = mu / nu_Q: level j scaled by the gain
+        const T e = fma(-c, (T)(2 * j - (M - 1)), v);   // c = mu / nu_Q: level j scaled by the gain
         const T d = e * e;
         const int gj = j ^ (j >> 1);
 #pragma unroll
@@ -52,15 +52,16 @@ __device__ __forceinline__ void axis_llr(T v, T c, T s, float* o) {
     }
 }
 
-template <int M, typename T>
-__global__ __launch_bounds__(256) void demap_kernel(int64_t n, int32_t R, const T* __restrict__ x,
+// IT: the symbol index type (32-bit where n allows: cheaper gain index i / R)
+template <int M, typename T, typename IT>
+__global__ __launch_bounds__(256) void demap_kernel(IT n, IT R, const T* __restrict__ x,
                                                     const float* __restrict__ gain, T inv_nu,
                                                     float* __restrict__ llr) {
     constexpr int NB = 2 * log2_of<M>();
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (IT i = blockIdx.x * (IT)blockDim.x + threadIdx.x; i < n; i += (IT)gridDim.x * blockDim.x) {
         // a non-finite component makes the whole symbol NaN (as its 2-D
         // distances are), not only that axis's bits
-        T xr = x[2 * i], xi = x[2 * i + 1];
+        T xr = x[2 * (int64_t)i], xi = x[2 * (int64_t)i + 1];
         const T poison = (xr - xr) + (xi - xi);
         xr += poison;
         xi += poison;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256) void demap_kernel(int64_t n, int32_t R, const 
         float o[NB];
         axis_llr<M, T>(xr, c, s, o);
         axis_llr<M, T>(xi, c, s, o + NB / 2);
-        float* dst = llr + i * NB;
+        float* dst = llr + (int64_t)i * NB;
         if constexpr (NB % 4 == 0) {
 #pragma unroll
             for (int k = 0; k < NB; k += 4) *reinterpret_cast<float4*>(dst + k) = make_float4(o[k], o[k + 1], o[k + 2], o[k + 3]);
@@ -90,17 +91,16 @@ unsigned demap_grid(int64_t n) {
     return (unsigned)b;
 }
 
-template <typename T>
-void launch_demap(hipStream_t s, int m, int64_t n, int32_t R, const void* x, const float* gain, double inv_nu,
-                  float* llr) {
+template <typename T, typename IT>
+void launch_demap(hipStream_t s, int m, IT n, IT R, const void* x, const float* gain, double inv_nu, float* llr) {
     const dim3 g(demap_grid(n)), b(256);
     const T* xp = static_cast<const T*>(x);
     const T in = (T)inv_nu;
     switch (m) {
-        case 2: hipLaunchKernelGGL((demap_kernel<2, T>), g, b, 0, s, n, R, xp, gain, in, llr); break;
-        case 4: hipLaunchKernelGGL((demap_kernel<4, T>), g, b, 0, s, n, R, xp, gain, in, llr); break;
-        case 8: hipLaunchKernelGGL((demap_kernel<8, T>), g, b, 0, s, n, R, xp, gain, in, llr); break;
-        default: hipLaunchKernelGGL((demap_kernel<16, T>), g, b, 0, s, n, R, xp, gain, in, llr); break;
+        case 2: hipLaunchKernelGGL((demap_kernel<2, T, IT>), g, b, 0, s, n, R, xp, gain, in, llr); break;
+        case 4: hipLaunchKernelGGL((demap_kernel<4, T, IT>), g, b, 0, s, n, R, xp, gain, in, llr); break;
+        case 8: hipLaunchKernelGGL((demap_kernel<8, T, IT>), g, b, 0, s, n, R, xp, gain, in, llr); break;
+        default: hipLaunchKernelGGL((demap_kernel<16, T, IT>), g, b, 0, s, n, R, xp, gain, in, llr); break;
     }
 }
 
@@ -123,8 +123,15 @@ extern "C" fpcg_status fpcg_demap_maxlog(void* stream, int64_t n, int32_t R, con
     const int m = (int)std::lround(std::sqrt((double)qam_order));
     const double inv_nu = 1.0 / std::sqrt(2.0 * (qam_order - 1) / 3.0);
     hipStream_t s = (hipStream_t)stream;
-    if (x_c64) launch_demap<float>(s, m, n, R, x, gain, inv_nu, llr);
-    else launch_demap<double>(s, m, n, R, x, gain, inv_nu, llr);
+    // 32-bit indices while the grid-stride loop cannot pass 2^32
+    const bool narrow = n <= (int64_t)UINT32_MAX - (int64_t)65535 * 256;
+    if (narrow) {
+        if (x_c64) launch_demap<float, uint32_t>(s, m, (uint32_t)n, (uint32_t)R, x, gain, inv_nu, llr);
+        else launch_demap<double, uint32_t>(s, m, (uint32_t)n, (uint32_t)R, x, gain, inv_nu, llr);
+    } else {
+        if (x_c64) launch_demap<float, int64_t>(s, m, n, (int64_t)R, x, gain, inv_nu, llr);
+        else launch_demap<double, int64_t>(s, m, n, (int64_t)R, x, gain, inv_nu, llr);
+    }
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(FPCG_E_DEVICE, "demap launch: %s", hipGetErrorString(err));
     return FPCG_OK;
