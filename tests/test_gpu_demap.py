@@ -204,3 +204,67 @@ def test_soft_output_full_size_sampled():
     assert np.all(np.abs(gs - g1) <= 4 * spread + 64 * 2.0**-24)
     ref = DM.maxlog_llr(xs, gs[..., None], q)
     _compare_llr(ls, ref, _llr_tolerance(xs, gs[..., None], q, 2.0**-24), 2.0**-24)
+
+
+def test_gain_depends_on_the_channel_only():
+    """Gains come from A alone: the same channels with R = 3 and R = 37 (three
+    workgroups per channel, only the first writes gains) give bitwise equal
+    gains; an indexed launch writes them for its channels only."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    B, K = 20, 32
+    wl3 = W.draw(B, 128, K, 3, 64, 18.0, 0.5, 0.5, seed=93)
+    wl37 = W.draw(B, 128, K, 37, 64, 18.0, 0.5, 0.5, seed=94)
+    _say("case gain vs R and indexed launch")
+    dev = torch.device("cuda:0")
+    Ht = torch.from_numpy(wl3.H.astype(np.complex64)).to(dev)
+    st = torch.from_numpy(wl3.sigma2).to(dev)
+    gains = []
+    for wl in (wl3, wl37):
+        Yt = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+        g = torch.full((B, K), -7.0, dtype=torch.float32, device=dev)
+        fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, gain=g)
+        torch.cuda.synchronize()
+        gains.append(g.cpu().numpy())
+    assert np.array_equal(gains[0].view(np.uint32), gains[1].view(np.uint32))
+    sel = np.array([3, 17, 0, 11], dtype=np.int32)
+    g = torch.full((B, K), -7.0, dtype=torch.float32, device=dev)
+    Yt = torch.from_numpy(wl3.Y.astype(np.complex64)).to(dev)
+    fp.detect(Ht, Yt, st, 64, 11, 4, "fp16", variant=2, gain=g, chan_idx=torch.from_numpy(sel).to(dev))
+    torch.cuda.synchronize()
+    gi = g.cpu().numpy()
+    assert np.array_equal(gi[sel].view(np.uint32), gains[0][sel].view(np.uint32))
+    assert np.all(np.delete(gi, sel, axis=0) == -7.0)
+
+
+def test_gain_fp8_large_k_with_refinement():
+    """K = 128, fp8 operands, L = 16, one FP64 refinement step (the c4 schedule):
+    gains against the oracle's from its own u_W Gram."""
+    wl = W.draw(6, 512, 128, 14, 256, 25.0, 0.9, 0.9, seed=95)
+    _say("case gain fp8 K=128 L=16 refine 1")
+    _, g, _ = _gain_gpu_sched(wl, np.complex64, 256, 32, 16, "fp8", refine=1)
+    r1 = oracle_detect(wl, 256, 32, 16, "fp8", io=np.complex64, refine=1, accum="exact")
+    r2 = oracle_detect(wl, 256, 32, 16, "fp8", io=np.complex64, refine=1, accum="sequential")
+    g1 = DM.effective_gain(r1.A, wl.sigma2, 16, "fp32")
+    spread = np.abs(g1 - DM.effective_gain(r2.A, wl.sigma2, 16, "fp32")).max()
+    tol = 4 * spread + 16 * 16 * 2.0**-24
+    _say(f"  gain gpu-oracle max {np.abs(g - g1).max():.2e}, oracle order spread {spread:.2e}")
+    assert np.all(np.abs(g - g1) <= tol)
+
+
+def _gain_gpu_sched(wl, io, qam, iters, L, sched, refine=0, variant=0):
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    dev = torch.device("cuda:0")
+    Ht = torch.from_numpy(np.ascontiguousarray(wl.H.astype(io))).to(dev)
+    Yt = torch.from_numpy(np.ascontiguousarray(wl.Y.astype(io))).to(dev)
+    st = torch.from_numpy(np.ascontiguousarray(wl.sigma2)).to(dev)
+    B, _, K = wl.H.shape
+    gain = torch.full((B, K), -7.0, dtype=torch.float32, device=dev)
+    x, lab, fl = fp.detect(Ht, Yt, st, qam, iters, L, sched, refine_steps=refine, variant=variant, gain=gain)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.complex128), gain.cpu().numpy().astype(np.float64), fl.cpu().numpy()
