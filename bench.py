@@ -77,6 +77,24 @@ def algorithmic_bytes(B, Nbs, K, R, elem=8, refine=0):
     return B * per
 
 
+def _host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"cpu_model": model, "cores_available": cores}
+
+
 def ber_of(labels, ref_labels, q):
     import torch
 
@@ -821,7 +839,8 @@ def main():
                 s0 = 0 if e == B else e
         cpu = {"value": round(nsamp * R / dt, 1), "unit": "detections/s", "cores": 1, "kind": "oracle",
                "sample": f"{nsamp} channels x {R} RHS of the same workload (chunks of 256, cycling over the batch), "
-                         f"FP64 CG (Alg. 2) with I={I64}, numpy batched over channels, one thread ({dt:.1f} s)"}
+                         f"FP64 CG (Alg. 2) with I={I64}, numpy batched over channels, one thread ({dt:.1f} s)",
+               "host": _host_cpu()}
 
     out = {
         "metric": "detections/sec (FP-BJ-CG vs FP64 CG) at BER parity; p50/p99 latency",
