@@ -201,6 +201,19 @@ def _stream_handle(stream, device):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _check_tensor(t, name, shape, dtype, device):
+    """Caller-supplied arrays are written or read by the kernels at the sizes
+    the call implies: reject anything else before a launch."""
+    if not getattr(t, "is_cuda", False) or t.device != device:
+        raise TypeError(f"{name} must be a CUDA tensor on {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
 def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Schedule" = "fp64",
            refresh_every: int = 0, refine_steps: int = 0, variant: int = 0,
            ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None, gain=None):
@@ -233,6 +246,8 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     R = Y.shape[2]
     if Y.shape[:2] != (B, Nbs) or sigma2.shape != (B,):
         raise ValueError("shape mismatch between H, Y and sigma2")
+    if Y.device != H.device or sigma2.device != H.device:
+        raise TypeError("H, Y and sigma2 must be on the same device")
     dev = H.device.index or 0
     ctx = ctx or _ctx_for(dev)
     if out is None:
@@ -241,14 +256,17 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         flags = torch.empty((B,), dtype=torch.int32, device=H.device)
     else:
         xhat, labels, flags = out
+        _check_tensor(xhat, "xhat", (B, K, R), H.dtype, H.device)
+        _check_tensor(labels, "labels", (B, K, R), torch.uint8, H.device)
+        _check_tensor(flags, "flags", (B,), torch.int32, H.device)
     if chan_idx is not None or kappa is not None or gain is not None:
-        if chan_idx is not None and (chan_idx.dtype != torch.int32 or not chan_idx.is_cuda):
-            raise TypeError("chan_idx must be an int32 CUDA tensor")
-        if kappa is not None and (kappa.dtype != torch.float32 or not kappa.is_cuda or kappa.shape != (B,)):
-            raise TypeError("kappa must be a float32 CUDA tensor of shape (B,)")
-        if gain is not None and (gain.dtype != torch.float32 or not gain.is_cuda or gain.shape != (B, K)
-                                 or not gain.is_contiguous()):
-            raise TypeError("gain must be a contiguous float32 CUDA tensor of shape (B, K)")
+        if chan_idx is not None:
+            if chan_idx.dtype != torch.int32 or not chan_idx.is_cuda or chan_idx.device != H.device:
+                raise TypeError("chan_idx must be an int32 CUDA tensor on the device of H")
+        if kappa is not None:
+            _check_tensor(kappa, "kappa", (B,), torch.float32, H.device)
+        if gain is not None:
+            _check_tensor(gain, "gain", (B, K), torch.float32, H.device)
         idx = chan_idx.contiguous() if chan_idx is not None else None
         _check(lib().fpcg_detect_ex(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                                     ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
@@ -274,6 +292,8 @@ def slice_qam(x, qam: int, stream=None):
     """QAM slicer on a complex CUDA tensor; uint8 labels of the same shape."""
     import torch
 
+    if not getattr(x, "is_cuda", False) or x.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("x must be a complex64 or complex128 CUDA tensor")
     x = x.contiguous()
     labels = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
     _check(lib().fpcg_slice(_stream_handle(stream, x.device), x.numel(), ctypes.c_void_p(x.data_ptr()),
@@ -287,14 +307,21 @@ def demap_maxlog(x, gain, qam: int, out=None, stream=None):
     (B, K, R, log2 qam), most significant label bit first."""
     import torch
 
+    if not getattr(x, "is_cuda", False) or x.dtype not in (torch.complex64, torch.complex128) or x.dim() != 3:
+        raise TypeError("x must be a complex64 or complex128 CUDA tensor (B, K, R)")
     x = x.contiguous()
-    if x.dim() != 3 or gain.shape != x.shape[:2] or gain.dtype != torch.float32 or not gain.is_cuda:
-        raise TypeError("x must be (B, K, R) and gain a float32 CUDA tensor (B, K)")
     nb = {4: 2, 16: 4, 64: 6, 256: 8}.get(qam)
     if nb is None:
         raise ValueError(f"qam={qam}")
+    if not getattr(gain, "is_cuda", False) or gain.device != x.device or gain.dtype != torch.float32 \
+            or tuple(gain.shape) != tuple(x.shape[:2]):
+        raise TypeError("gain must be a float32 CUDA tensor (B, K) on the device of x")
     gain = gain.contiguous()
-    llr = out if out is not None else torch.empty(tuple(x.shape) + (nb,), dtype=torch.float32, device=x.device)
+    if out is None:
+        llr = torch.empty(tuple(x.shape) + (nb,), dtype=torch.float32, device=x.device)
+    else:
+        _check_tensor(out, "out", tuple(x.shape) + (nb,), torch.float32, x.device)
+        llr = out
     _check(lib().fpcg_demap_maxlog(_stream_handle(stream, x.device), x.numel(), x.shape[2],
                                    ctypes.c_void_p(x.data_ptr()), 1 if x.dtype == torch.complex64 else 0,
                                    ctypes.c_void_p(gain.data_ptr()), qam, ctypes.c_void_p(llr.data_ptr())))
@@ -305,6 +332,10 @@ def round_operand(x, fmt: str, scale: float = 1.0, stream=None):
     """fl(.) of the detector's operand conversion on a float32 CUDA tensor."""
     import torch
 
+    if not getattr(x, "is_cuda", False) or x.dtype != torch.float32:
+        raise TypeError("x must be a float32 CUDA tensor")
+    if fmt not in FMT:
+        raise ValueError(f"unknown format {fmt!r}")
     x = x.contiguous()
     out = torch.empty_like(x)
     _check(lib().fpcg_round(_stream_handle(stream, x.device), x.numel(), ctypes.c_void_p(x.data_ptr()),

@@ -268,3 +268,40 @@ def _gain_gpu_sched(wl, io, qam, iters, L, sched, refine=0, variant=0):
     x, lab, fl = fp.detect(Ht, Yt, st, qam, iters, L, sched, refine_steps=refine, variant=variant, gain=gain)
     torch.cuda.synchronize()
     return x.cpu().numpy().astype(np.complex128), gain.cpu().numpy().astype(np.float64), fl.cpu().numpy()
+
+
+def test_binding_rejects_mismatched_outputs():
+    """Caller-supplied outputs of the wrong shape, dtype or layout are
+    rejected before any launch (the kernels write at the sizes the call implies)."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    dev = torch.device("cuda:0")
+    wl = W.draw(4, 32, 8, 3, 16, 15.0, 0.3, 0.3, seed=96)
+    H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    s2 = torch.from_numpy(wl.sigma2).to(dev)
+    good = (torch.empty((4, 8, 3), dtype=torch.complex64, device=dev), torch.empty((4, 8, 3), dtype=torch.uint8, device=dev),
+            torch.empty((4,), dtype=torch.int32, device=dev))
+    bad = [(torch.empty((4, 8, 2), dtype=torch.complex64, device=dev),) + good[1:],
+           (good[0].to(torch.complex128),) + good[1:],
+           (good[0], good[1][:, :, :2], good[2]),
+           (good[0], good[1], torch.empty((3,), dtype=torch.int32, device=dev)),
+           (torch.empty((4, 3, 8), dtype=torch.complex64, device=dev).transpose(1, 2),) + good[1:]]
+    for o in bad:
+        with pytest.raises((TypeError, ValueError)):
+            fp.detect(H, Y, s2, 16, 4, 4, "fp16", out=o)
+    with pytest.raises((TypeError, ValueError)):
+        fp.detect(H, Y, s2, 16, 4, 4, "fp16", gain=torch.empty((4, 7), dtype=torch.float32, device=dev))
+    x, _, _ = fp.detect(H, Y, s2, 16, 4, 4, "fp16", out=good)
+    g = torch.full((4, 8), 0.5, dtype=torch.float32, device=dev)
+    for o in (torch.empty((4, 8, 3, 2), dtype=torch.float32, device=dev),
+              torch.empty((4, 8, 3, 4), dtype=torch.float64, device=dev)):
+        with pytest.raises((TypeError, ValueError)):
+            fp.demap_maxlog(x, g, 16, out=o)
+    with pytest.raises(TypeError):
+        fp.demap_maxlog(x.real.contiguous(), g, 16)
+    with pytest.raises(TypeError):
+        fp.slice_qam(x.real.contiguous(), 16)
+    torch.cuda.synchronize()
