@@ -361,23 +361,34 @@ def soft_bench(args, steps=30, rounds=3):
     plain = lambda: fp.detect(H, Y, s2, q, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=stream)
     withg = lambda: fp.detect(H, Y, s2, q, 11, 4, "fp16", variant=2, ctx=ctx, out=out, stream=stream, gain=gain)
     demap = lambda: fp.demap_maxlog(out[0], gain, q, out=llr, stream=stream)
+    llr8 = torch.empty((B, K, R, nb), dtype=torch.int8, device=dev)
+    demap8 = lambda: fp.demap_maxlog(out[0], gain, q, out=llr8, stream=stream, scale=8.0)
 
     def soft():
         withg()
         demap()
 
-    tp, tg, td, ts = [], [], [], []
+    def soft8():
+        withg()
+        demap8()
+
+    tp, tg, td, ts, td8, ts8 = [], [], [], [], [], []
     for _ in range(rounds):
         tp.append(timed(plain))
         tg.append(timed(withg))
         td.append(timed(demap, 3 * steps))
         ts.append(timed(soft))
-    tp, tg, td, ts = (np.concatenate(t) for t in (tp, tg, td, ts))
+        td8.append(timed(demap8, 3 * steps))
+        ts8.append(timed(soft8))
+    tp, tg, td, ts, td8, ts8 = (np.concatenate(t) for t in (tp, tg, td, ts, td8, ts8))
     n_sym = B * K * R
     dbytes = n_sym * (8 + 4 * nb) + B * K * 4
     ach = dbytes / (float(np.mean(td)) * 1e-3) / 1e9
+    dbytes8 = n_sym * (8 + nb) + B * K * 4
+    ach8 = dbytes8 / (float(np.mean(td8)) * 1e-3) / 1e9
     log(f"c2 fp16 L=4 I=11: detection p50 {np.median(tp):.4f} ms, with gains {np.median(tg):.4f} ms, "
-        f"demap p50 {np.median(td):.4f} ms ({ach:.0f} GB/s mean), detection + demap {np.median(ts):.4f} ms")
+        f"demap p50 {np.median(td):.4f} ms ({ach:.0f} GB/s mean), detection + demap {np.median(ts):.4f} ms; "
+        f"int8 LLRs: demap p50 {np.median(td8):.4f} ms ({ach8:.0f} GB/s mean), detection + demap {np.median(ts8):.4f} ms")
     res["c2"] = {"schedule": "fp16", "L": 4, "variant": 2, "iters": 11, "B": B, "qam": q,
                  "detect_p50_ms": round(float(np.median(tp)), 5),
                  "detect_with_gain_p50_ms": round(float(np.median(tg)), 5),
@@ -385,8 +396,14 @@ def soft_bench(args, steps=30, rounds=3):
                  "soft_path_p50_ms": round(float(np.median(ts)), 5),
                  "soft_detections_per_s": round(B * R / (float(np.median(ts)) * 1e-3), 1),
                  "demap_roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                    "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": dbytes}}
-    del H, Y, s2, out, gain, llr
+                                    "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": dbytes},
+                 "demap_int8_p50_ms": round(float(np.median(td8)), 5), "demap_int8_mean_ms": round(float(np.mean(td8)), 5),
+                 "soft_path_int8_p50_ms": round(float(np.median(ts8)), 5),
+                 "soft_int8_detections_per_s": round(B * R / (float(np.median(ts8)) * 1e-3), 1),
+                 "demap_int8_roofline": {"bound": "hbm", "achieved": round(ach8, 1), "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": round(ach8 / HBM_PEAK_GBS, 4),
+                                         "bytes_per_launch": dbytes8}}
+    del H, Y, s2, out, gain, llr, llr8
     torch.cuda.empty_cache()
 
     # ---------------------------------------------------------------- LLR quality, the coded setting

@@ -230,6 +230,16 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
 fpcg_status fpcg_demap_maxlog(void* stream, int64_t n, int32_t R, const void* x, int32_t x_c64,
                               const float* gain, int32_t qam_order, float* llr);
 
+/* The same LLRs as 8-bit integers, the input width of common decoders:
+ * llr[i][b] = clamp(rint(LLR * scale), -127, 127) with the float LLR of
+ * fpcg_demap_maxlog, its product with scale rounded to FP32 and then to the
+ * nearest integer (ties to even); a NaN LLR becomes 0.  scale: finite, > 0
+ * (e.g. 127 / the largest LLR magnitude the decoder should resolve).
+ * llr: device, 8-byte aligned, n * log2(Q) bytes, same order as the float
+ * form.  Errors as fpcg_demap_maxlog, plus FPCG_E_INVAL for a bad scale. */
+fpcg_status fpcg_demap_maxlog_i8(void* stream, int64_t n, int32_t R, const void* x, int32_t x_c64,
+                                 const float* gain, int32_t qam_order, float scale, int8_t* llr);
+
 /* QAM slicer on its own (the detector's epilogue): nearest unit-energy
  * square-QAM point per complex value, decided in FP32 (x_c64 != 0) or FP64.
  * Per axis j = clamp(floor((v nu + m) / 2), 0, m - 1), nu = sqrt(2 (Q-1) / 3),

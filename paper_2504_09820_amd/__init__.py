@@ -102,6 +102,8 @@ def lib():
     L.fpcg_detect_ex.restype = st
     L.fpcg_demap_maxlog.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp]
     L.fpcg_demap_maxlog.restype = st
+    L.fpcg_demap_maxlog_i8.argtypes = [vp, i64, i32, vp, i32, vp, i32, ctypes.c_float, vp]
+    L.fpcg_demap_maxlog_i8.restype = st
     L.fpcg_slice.argtypes = [vp, i64, vp, i32, i32, vp]
     L.fpcg_slice.restype = st
     L.fpcg_round.argtypes = [vp, i64, vp, i32, ctypes.c_float, vp]
@@ -301,10 +303,11 @@ def slice_qam(x, qam: int, stream=None):
     return labels
 
 
-def demap_maxlog(x, gain, qam: int, out=None, stream=None):
+def demap_maxlog(x, gain, qam: int, out=None, stream=None, scale=None):
     """Max-log LLRs (fpcg_demap_maxlog) of the estimates x (B, K, R) complex
     CUDA tensor with the detector's gains (B, K) float32: float32 tensor
-    (B, K, R, log2 qam), most significant label bit first."""
+    (B, K, R, log2 qam), most significant label bit first.  With `scale`, the
+    LLRs as saturated int8 values round(LLR * scale) (fpcg_demap_maxlog_i8)."""
     import torch
 
     if not getattr(x, "is_cuda", False) or x.dtype not in (torch.complex64, torch.complex128) or x.dim() != 3:
@@ -317,11 +320,18 @@ def demap_maxlog(x, gain, qam: int, out=None, stream=None):
             or tuple(gain.shape) != tuple(x.shape[:2]):
         raise TypeError("gain must be a float32 CUDA tensor (B, K) on the device of x")
     gain = gain.contiguous()
+    odt = torch.float32 if scale is None else torch.int8
     if out is None:
-        llr = torch.empty(tuple(x.shape) + (nb,), dtype=torch.float32, device=x.device)
+        llr = torch.empty(tuple(x.shape) + (nb,), dtype=odt, device=x.device)
     else:
-        _check_tensor(out, "out", tuple(x.shape) + (nb,), torch.float32, x.device)
+        _check_tensor(out, "out", tuple(x.shape) + (nb,), odt, x.device)
         llr = out
+    if scale is not None:
+        _check(lib().fpcg_demap_maxlog_i8(_stream_handle(stream, x.device), x.numel(), x.shape[2],
+                                          ctypes.c_void_p(x.data_ptr()), 1 if x.dtype == torch.complex64 else 0,
+                                          ctypes.c_void_p(gain.data_ptr()), qam, float(scale),
+                                          ctypes.c_void_p(llr.data_ptr())))
+        return llr
     _check(lib().fpcg_demap_maxlog(_stream_handle(stream, x.device), x.numel(), x.shape[2],
                                    ctypes.c_void_p(x.data_ptr()), 1 if x.dtype == torch.complex64 else 0,
                                    ctypes.c_void_p(gain.data_ptr()), qam, ctypes.c_void_p(llr.data_ptr())))

@@ -167,3 +167,9 @@ def test_demap_validates_on_the_host(fp):
     assert L.fpcg_demap_maxlog(None, 4, 1, p, 1, p, 16, None) == -1
     assert L.fpcg_demap_maxlog(None, 4, 1, p, 1, p, 16, al + 4) == -1             # llr not 16-byte aligned
     assert "aligned" in L.fpcg_last_error().decode()
+    i8 = L.fpcg_demap_maxlog_i8
+    assert i8(None, 0, 1, None, 1, None, 64, 4.0, None) == 0
+    for sc in (0.0, -1.0, float("inf"), float("nan")):
+        assert i8(None, 4, 1, p, 1, p, 16, sc, al) == -1
+    assert i8(None, 4, 1, p, 1, p, 16, 4.0, al + 4) == -1                         # int8 LLRs 8-byte aligned
+    assert i8(None, 4, 0, p, 1, p, 16, 4.0, al) == -1

@@ -305,3 +305,46 @@ def test_binding_rejects_mismatched_outputs():
     with pytest.raises(TypeError):
         fp.slice_qam(x.real.contiguous(), 16)
     torch.cuda.synchronize()
+
+
+def _quant8(llr32, scale):
+    """round(LLR * scale) to nearest even in FP32, NaN -> 0, clamped to +-127."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        t = np.asarray(llr32, dtype=np.float32) * np.float32(scale)
+    t = np.where(np.isnan(t), np.float32(0), t)
+    return np.clip(np.rint(t), -127, 127).astype(np.int8)
+
+
+@pytest.mark.parametrize("io", [np.complex64, np.complex128])
+@pytest.mark.parametrize("q", [4, 16, 64, 256])
+def test_demap_int8(q, io):
+    """8-bit LLRs: bitwise the quantisation of the float demapper's own output
+    (same FP32 product and rounding), and within one step of the quantised
+    oracle LLRs; saturation, NaN -> 0 and the degenerate gains included."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    rng = np.random.default_rng(40 + q + (io == np.complex128))
+    B, K, R = 9, 7, 11                                    # 693 symbols, ragged
+    x = ((rng.standard_normal((B, K, R)) + 1j * rng.standard_normal((B, K, R))) * 0.9).astype(io)
+    gain = rng.uniform(0.02, 0.999, (B, K)).astype(np.float32)
+    gain[0, :3] = [0.0, 1.0, 0.9999]                      # no signal, zero-forcing (+-inf), huge LLRs (saturate)
+    gain[1, 0] = np.nan
+    x[2, 0, 0] = np.nan
+    _say(f"case demap int8 q={q} io={np.dtype(io).name}")
+    dev = torch.device("cuda:0")
+    xt = torch.from_numpy(x).to(dev)
+    gt = torch.from_numpy(gain).to(dev)
+    for scale in (4.0, 0.37):
+        l32 = fp.demap_maxlog(xt, gt, q)
+        l8 = fp.demap_maxlog(xt, gt, q, scale=scale)
+        torch.cuda.synchronize()
+        got = l8.cpu().numpy()
+        assert got.dtype == np.int8
+        np.testing.assert_array_equal(got, _quant8(l32.cpu().numpy(), scale))
+        ref = DM.maxlog_llr(x.astype(np.complex128), gain.astype(np.float64)[..., None], q)
+        qo = _quant8(ref.astype(np.float32), scale).astype(np.int32)
+        assert np.max(np.abs(got.astype(np.int32) - qo)) <= 1
+        assert np.all(got[np.isnan(ref)] == 0)
+    assert np.any(np.abs(got) == 127)                     # saturation was exercised
