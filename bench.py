@@ -437,6 +437,66 @@ def soft_bench(args, steps=30, rounds=3):
     print(json.dumps(res))
 
 
+def io_compare_bench(args, steps=30, rounds=3):
+    """The timed schedules with complex64 against complex128 inputs (the
+    latter doubles the bytes the mixed path must read): c2 (fp16, L = 4,
+    symmetric form, I = 11; FP64 CG I = 15) and c3 (fp32, L = 4, symmetric
+    form, I = 20; FP64 CG I = 27), p50 and mean per launch and the mixed
+    path's algorithmic bandwidth.  One JSON line."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = fp.Context(0)
+    res = {"mode": "io_compare"}
+
+    def timed(fn, n=steps):
+        torch.cuda.synchronize()
+        time.sleep(IDLE_S)
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+
+    for cfg, mixed, i_mp, i_64 in (("c2", "fp16", 11, 15), ("c3", "fp32", 20, 27)):
+        c = W.CONFIGS[cfg]
+        B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
+        wl = W.draw(B, Nbs, K, R, q, c["snr_db"], c["zeta"], c["zeta"], seed=2504_09820 * 10 + int(cfg[-1]),
+                    normalization=c["normalization"])
+        s2 = torch.from_numpy(wl.sigma2).to(dev)
+        row = {"B": B, "Nbs": Nbs, "K": K, "R": R, "mixed": f"{mixed}, L=4, symmetric, I={i_mp}", "fp64_iters": i_64}
+        for io, tio, es in (("complex64", torch.complex64, 8), ("complex128", torch.complex128, 16)):
+            H = torch.from_numpy(wl.H).to(dev).to(tio)
+            Y = torch.from_numpy(wl.Y).to(dev).to(tio)
+            out = (torch.empty((B, K, R), dtype=tio, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
+                   torch.empty((B,), dtype=torch.int32, device=dev))
+            tm, t64 = [], []
+            for _ in range(rounds):
+                tm.append(timed(lambda: fp.detect(H, Y, s2, q, i_mp, 4, mixed, variant=2, ctx=ctx, out=out, stream=stream)))
+                t64.append(timed(lambda: fp.detect(H, Y, s2, q, i_64, 0, "fp64", ctx=ctx, out=out, stream=stream)))
+            tm, t64 = np.concatenate(tm), np.concatenate(t64)
+            nbytes = algorithmic_bytes(B, Nbs, K, R, elem=es)
+            row[io] = {"mixed_p50_ms": round(float(np.median(tm)), 5), "mixed_mean_ms": round(float(np.mean(tm)), 5),
+                       "fp64_p50_ms": round(float(np.median(t64)), 5),
+                       "speedup": round(float(np.median(t64) / np.median(tm)), 3),
+                       "mixed_gbs": round(nbytes / (float(np.mean(tm)) * 1e-3) / 1e9, 1), "bytes_per_launch": nbytes}
+            log(f"{cfg} {io}: mixed p50 {np.median(tm):.4f} ms ({row[io]['mixed_gbs']:.0f} GB/s), "
+                f"FP64 CG p50 {np.median(t64):.4f} ms, speedup {row[io]['speedup']:.2f}")
+            del H, Y, out
+            torch.cuda.empty_cache()
+        res[cfg] = row
+    print(json.dumps(res))
+
+
 def robust_bench(args, B=4096, snr_db=26.7):
     """Robustness workloads of Sec. V at c2's shape (Nbs = 128, K = 32, 64-QAM,
     14 received vectors), at the SNR of c2's BER-1e-3 operating point: bit error
@@ -624,6 +684,8 @@ def main():
                          "loop; p50/p99 request latency and throughput at several offered loads")
     ap.add_argument("--robust", action="store_true",
                     help="robustness workloads: BER with imperfect CSI, geometry channels, Gauss-Markov variation")
+    ap.add_argument("--io-compare", action="store_true",
+                    help="the timed schedules with complex64 against complex128 inputs (c2, c3)")
     ap.add_argument("--soft", action="store_true",
                     help="soft output: gain output and max-log demapper timed at c2, LLR quality over SNR")
     ap.add_argument("--kappa-profile", action="store_true", help="with --profile: also the launches with kappa output")
@@ -650,6 +712,9 @@ def main():
         return
     if args.soft and args.gpus == 1:
         soft_bench(args)
+        return
+    if args.io_compare and args.gpus == 1:
+        io_compare_bench(args)
         return
 
     if args.gpus != 1:
