@@ -164,9 +164,12 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static_assert(AROW || sz_X <= 2 * W * KP * LDA, "x fits the Gram's slot");
     static constexpr size_t sz_B = 2 * W * KP * 16;
     static constexpr bool B_FITS = sz_X + sz_B <= 2 * W * KP * LDA;   // x and B in the Gram's slot
-    // Once A sits in registers and no FP64 refresh reads the stored Gram, the
-    // Gram's LDS is dead after the operand is packed and x moves into it.
-    __host__ __device__ static constexpr bool x_in_gram(int refresh_every) { return AREG && refresh_every == 0; }
+    // Once A's operand copy is packed (into registers, or into its own LDS
+    // fragment region) and no FP64 refresh reads the stored Gram, the Gram's
+    // LDS is dead and x moves into it.
+    __host__ __device__ static constexpr bool x_in_gram(int refresh_every) {
+        return (AREG || AFRAG_LDS) && refresh_every == 0;
+    }
     // Compact layout (one workgroup per channel, no refinement, x in the Gram's
     // slot): B is carried in registers through the block-Jacobi setup and then
     // stored next to x, so the layout is [A (then x, B) | M | F | S].

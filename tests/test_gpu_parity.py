@@ -144,6 +144,11 @@ CASES = [
     ("c3-fp64-L8-split", 5, 256, 64, 14, 64, 15.0, 0.7, 24, 8, "fp64", np.complex128, 0, 2),
     ("c3-fp16-L8-split-refresh4", 5, 256, 64, 14, 64, 15.0, 0.7, 16, 8, "fp16", np.complex64, 4, 2),
     ("c3-fp8-L8-split", 5, 256, 64, 14, 64, 15.0, 0.7, 16, 8, "fp8", np.complex64, 0, 2),
+    # K = 64 with the operand fragments in LDS and no refresh: x lives in the Gram's slot
+    ("c3-fp16-L4-split", 5, 256, 64, 14, 64, 15.0, 0.7, 16, 4, "fp16", np.complex64, 0, 2),
+    ("c3-bf16-L0", 5, 256, 64, 14, 64, 15.0, 0.7, 16, 0, "bf16", np.complex64, 0, 0),
+    ("c3-fp16-L8-R20", 4, 256, 64, 20, 64, 15.0, 0.7, 16, 8, "fp16", np.complex64, 0, 0),
+    ("K64-N200-R9-fp16-L8-textbook-c128", 4, 200, 64, 9, 16, 18.0, 0.5, 14, 8, "fp16", np.complex128, 0, 1),
     ("ragged-K20-N50-R17-fp32-L4-split", 5, 50, 20, 17, 16, 15.0, 0.3, 12, 4, "fp32", np.complex128, 0, 2),
     ("ragged-K12-N40-R3-bf16-L4-split-refresh3", 5, 40, 12, 3, 256, 25.0, 0.2, 10, 4, "bf16", np.complex64, 3, 2),
     # K up to 128: two waves per channel, A kept only in the operand format
@@ -172,9 +177,9 @@ def test_fixed_iteration_parity(case):
 # --------------------------------------------------------------- refinement
 @pytest.mark.parametrize("sched,steps,variant", [("fp16", 1, 0), ("fp8", 1, 0), ("fp8", 2, 0), ("bf16", 2, 0),
                                                  ("fp32", 1, 0), ("fp16", 1, 2), ("fp8", 2, 2)])
-def test_refinement_reaches_oracle_accuracy(sched, steps, variant):
-    _say(f"case refine {sched} x{steps} variant={variant}")
-    wl = _wl(8, 128, 32, 14, 64, 25.0, 0.5, 21)
+def test_refinement_reaches_oracle_accuracy(sched, steps, variant, K=32, Nbs=128):
+    _say(f"case refine {sched} x{steps} variant={variant} K={K}")
+    wl = _wl(8, Nbs, K, 14, 64, 25.0, 0.5, 21)
     x, lab, fl = gpu_detect(wl, 64, 16, 8, sched, np.complex64, refine=steps, variant=variant)
     ref = oracle_detect(wl, 64, 16, 8, sched, np.complex64, refine=steps, variant=variant)
     A, b = D.gram(wl.H.astype(np.complex64).astype(np.complex128), wl.Y.astype(np.complex64).astype(np.complex128),
@@ -188,6 +193,13 @@ def test_refinement_reaches_oracle_accuracy(sched, steps, variant):
     d = boundary_distance(xs, 64)
     must = d > 1e-3 + np.abs(x - xs)
     assert np.array_equal(lab[must], D.slice_qam(xs, 64)[must])
+
+
+@pytest.mark.parametrize("sched,variant", [("fp16", 0), ("bf16", 1)])
+def test_refinement_at_k64(sched, variant):
+    """K = 64: the FP64 iterate and x share the LDS with the packed operand
+    (x in the Gram's slot); one refinement step to the oracle's accuracy."""
+    test_refinement_reaches_oracle_accuracy(sched, 1, variant, K=64, Nbs=256)
 
 
 # --------------------------------------------------------------- edge cases
