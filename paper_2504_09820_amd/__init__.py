@@ -389,18 +389,28 @@ class Server:
         import numpy as np
 
         sched = schedule(schedule_, refresh_every, refine_steps, variant) if isinstance(schedule_, str) else schedule_
+        # the library copies B*Nbs*R elements of Y (and B*Nbs*K of H, B of
+        # sigma2) from these host arrays: every shape is checked here first
         if channels is not None:
+            if channels not in self._chans:
+                raise ValueError(f"unknown channel-set handle {channels}")
             B, Nbs, K, dt = self._chans[channels]
             Y = np.ascontiguousarray(Y, dtype=dt)
             H = s2 = None
             hp = sp = None
         else:
             H = np.ascontiguousarray(H)
+            if H.dtype not in (np.complex64, np.complex128) or H.ndim != 3:
+                raise TypeError("H must be a complex64 or complex128 array (B, Nbs, K)")
             Y = np.ascontiguousarray(Y, dtype=H.dtype)
             s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
             B, Nbs, K = H.shape
             dt = H.dtype
+            if s2.shape != (B,):
+                raise ValueError(f"sigma2 must have shape ({B},), got {s2.shape}")
             hp, sp = H.ctypes.data, s2.ctypes.data
+        if Y.ndim != 3 or Y.shape[:2] != (B, Nbs):
+            raise ValueError(f"Y must have shape ({B}, {Nbs}, R), got {Y.shape}")
         R = Y.shape[2]
         xhat = np.empty((B, K, R), dtype=dt)
         labels = np.empty((B, K, R), dtype=np.uint8)

@@ -173,3 +173,41 @@ def test_demap_validates_on_the_host(fp):
         assert i8(None, 4, 1, p, 1, p, 16, sc, al) == -1
     assert i8(None, 4, 1, p, 1, p, 16, 4.0, al + 4) == -1                         # int8 LLRs 8-byte aligned
     assert i8(None, 4, 0, p, 1, p, 16, 4.0, al) == -1
+
+
+def _bare_server(fp, chans=None):
+    """A Server object with a NULL library handle: the binding's own checks run,
+    and anything that reaches the library is refused there (NULL server)."""
+    srv = fp.Server.__new__(fp.Server)
+    srv._h = ctypes.c_void_p()
+    srv._keep = {}
+    srv._chans = dict(chans or {})
+    return srv
+
+
+def test_server_submit_validates_shapes_before_the_library(fp):
+    import numpy as np
+
+    srv = _bare_server(fp, {7: (4, 16, 8, np.complex64)})
+    H = np.zeros((4, 16, 8), np.complex64)
+    Y = np.zeros((4, 16, 3), np.complex64)
+    s2 = np.ones(4)
+    bad = [
+        dict(H=H, Y=np.zeros((3, 16, 3), np.complex64), sigma2=s2),     # B of Y differs
+        dict(H=H, Y=np.zeros((4, 15, 3), np.complex64), sigma2=s2),     # Nbs of Y differs
+        dict(H=H, Y=np.zeros((4, 16), np.complex64), sigma2=s2),        # Y not 3-D
+        dict(H=H, Y=Y, sigma2=np.ones(3)),                              # sigma2 too short
+        dict(H=H, Y=Y, sigma2=np.ones((4, 1))),                         # sigma2 not (B,)
+        dict(H=np.zeros((4, 16, 8), np.float32), Y=Y, sigma2=s2),       # H not complex
+        dict(H=None, Y=np.zeros((4, 17, 3), np.complex64), sigma2=None, channels=7),   # resident set: Nbs
+        dict(H=None, Y=np.zeros((2, 16, 3), np.complex64), sigma2=None, channels=7),   # resident set: B
+        dict(H=None, Y=Y, sigma2=None, channels=8),                                    # unknown handle
+    ]
+    for kw in bad:
+        with pytest.raises((ValueError, TypeError)):
+            srv.submit(qam=16, iters=4, **kw)
+    # consistent shapes reach the library, which refuses the NULL server
+    with pytest.raises(fp.FpcgError):
+        srv.submit(H, Y, s2, 16, 4)
+    with pytest.raises(fp.FpcgError):
+        srv.submit(None, Y, None, 16, 4, channels=7)
