@@ -1,30 +1,34 @@
 """Throughput benchmark of the fused finite-precision (block-Jacobi) CG detector
 on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--schedule auto] [--L auto]
+    python bench.py [--steps K] [--warmup W] [--config c3] [--schedule auto] [--L auto]
 
-Workload (default c2): Nbs = 128 BS antennas, K = 32 streams, R = 14 received
-vectors per channel, B = 16384 channels, Kronecker exponential correlation
-0.5 at both ends, 64-QAM, SNR 20 dB; synthetic and seeded, complex64 inputs
+Workload (default c3): Nbs = 256 BS antennas, K = 64 streams, R = 14 received
+vectors per channel, B = 8192 channels, Kronecker exponential correlation
+0.7 at both ends, 64-QAM, SNR 15 dB; synthetic and seeded, complex64 inputs
 resident in HBM before the timed region.
 
 One step = one call of the detector over the whole batch (Gram + matched
-filter, block-Jacobi setup, the CG iterations, slicer), one fused kernel
-launch.  The method timed is FP-BJ-CG (Alg. 3 in its symmetric form): the
-operand format is the one the precision heuristic (eq. heuristic_bj) selects
-for the expected condition number of the preconditioned system, the Jacobi
-block size is the faster of L = 4 and L = 8 at BER parity, and the iteration
-counts come from a BER-parity search at the 1e-3 operating point: on a
-4096-channel slice of the batch (its channels, symbols and noise realisation
-kept, the noise rescaled) the SNR where the converged (3K-iteration) FP64 solve
-crosses BER 1e-3 is found, and there
+filter, block-Jacobi setup, the CG iterations with their FP64 residual
+refreshes, slicer), one fused kernel launch, replayed from a captured HIP
+graph.  The schedules timed are the workload's configured ones (c3: FP-BJ-CG,
+Alg. 3 in its symmetric form, fp16 operands, FP32 alpha/beta and vectors, an
+FP64 residual refresh every 4 iterations, Jacobi blocks of 4 and of 8; the
+faster is reported); the format the precision heuristic (eq. heuristic_bj)
+selects for the expected condition number is timed beside them.  Every
+schedule runs in the launch form (waves per channel, fused or pipelined) the
+library's autotuner picks for its shape class.  Iteration counts come from a
+BER-parity search at the 1e-3 operating point: on a 4096-channel slice of the
+batch (its channels, symbols and noise realisation kept, the noise rescaled)
+the SNR where the converged (3K-iteration) FP64 solve crosses BER 1e-3 is
+found, and there
     I64 = smallest I whose FP64 CG bit-error rate is within 2 % of the converged one,
-    Imp = smallest I whose FP-BJ-CG bit-error rate is within 2 % of FP64 CG's at I64.
-The SNR gap at BER 1e-3 between FP-BJ-CG (Imp) and FP64 CG (I64) is reported.
-FP64 CG (Alg. 2, FP64 matrix cores) is timed at I64 on the same batch and GPU.
-The board lowers its clocks after a few milliseconds of sustained load, so
-both timed runs start from the same state: 2 s without work, then their
-warmup launches, then the timed launches (of similar total duration).
+    Imp = smallest I whose mixed-precision bit-error rate is within 2 % of FP64 CG's at I64.
+The SNR gap at BER 1e-3 between the mixed schedule (Imp) and FP64 CG (I64) is
+reported.  FP64 CG (Alg. 2, FP64 matrix cores) is timed at I64 on the same
+batch and GPU.  The board lowers its clocks after a few milliseconds of
+sustained load, so every timed run starts from the same state: a few seconds
+without work, then its warmup replays, then the timed replays.
 
 Prints one JSON line on stdout; everything else goes to stderr.
 """
@@ -138,14 +142,19 @@ def write_traffic(args, fetch_csv, write_csv):
         scale = (1 << 30) / (float(np.mean(copies)) * 1024)
         res[counter] = {"kib_per_launch_raw": float(np.mean(fused)), "copy_kib_raw": float(np.mean(copies)),
                         "scale": scale, "bytes_per_launch": float(np.mean(fused)) * 1024 * scale}
-    L = int(args.L) if args.L != "auto" else 4
-    it = args.iters or 11
-    rec = {"config": args.config, "schedule": args.schedule, "L": L, "variant": args.variant, "iters": it,
+    cd = dict(CONFIGURED[args.config][0])
+    if args.schedule != "auto":
+        cd = dict(sched=args.schedule, L=0 if args.L == "auto" else int(args.L), refresh=args.refresh,
+                  refine=args.refine, variant=args.variant)
+    L = cd["L"]
+    it = args.iters or FIXED_ITERS.get(args.config) or 16
+    rec = {"config": args.config, "schedule": cd["sched"], "L": L, "variant": cd["variant"], "iters": it,
+           "refresh": cd["refresh"], "refine": cd["refine"],
            "kernel_source_hash": kernel_source_hash(),
            "hbm_bytes_per_launch": round(res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]),
            "counters": res, "sources": [os.path.basename(fetch_csv), os.path.basename(write_csv)]}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    path = traffic_file(args.config, args.schedule, L, args.variant, it)
+    path = traffic_file(args.config, cd["sched"], L, cd["variant"], it)
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     log(f"wrote {path}: {rec['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch")
@@ -275,7 +284,7 @@ def kappa_bench(args, steps=30, rounds=3):
     Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
     s2 = torch.from_numpy(wl.sigma2).to(dev)
     tx = torch.from_numpy(wl.labels.astype(np.uint8)).to(dev)
-    ekap = precision.expected_kappa(wl.H.astype(np.complex64), wl.sigma2, L, sample=64)
+    ekap = precision.expected_kappa(wl.H.astype(np.complex64), wl.Y.astype(np.complex64), wl.sigma2, L, sample=64)
     fmt_e, ub = precision.choose_format(K, ekap)
     kap = torch.empty((B,), dtype=torch.float32, device=dev)
     out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
@@ -545,7 +554,7 @@ def robust_bench(args, B=4096, snr_db=26.7):
     seq = []
     prev = None
     for i, wl in enumerate(steps):
-        ek = precision.expected_kappa(wl.H.astype(np.complex64), wl.sigma2, 4, sample=64)
+        ek = precision.expected_kappa(wl.H.astype(np.complex64), wl.Y.astype(np.complex64), wl.sigma2, 4, sample=64)
         f, _ = precision.choose_format(K, ek)
         fmt0 = fmt0 or f
         H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
@@ -594,7 +603,7 @@ def serve_bench(args, n_pool=24, n_requests=400, seed=5):
         wl = W.draw(B, Nbs, K, 14, 64, float(rng.uniform(5, 25)), zeta, zeta, seed=9000 + i)
         key = (Nbs, K, round(zeta, 1))
         if key not in fmt_cache:
-            fmt_cache[key] = precision.choose_format(K, precision.expected_kappa(wl.H, wl.sigma2, 4, sample=16))[0]
+            fmt_cache[key] = precision.choose_format(K, precision.expected_kappa(wl.H, wl.Y, wl.sigma2, 4, sample=16))[0]
         pool.append(dict(H=wl.H.astype(np.complex64), Y=wl.Y.astype(np.complex64), s2=wl.sigma2, B=B, K=K, Nbs=Nbs,
                          sched=fmt_cache[key]))
     log(f"serving pool: {n_pool} requests drawn in {time.time() - t0:.1f} s; formats "
@@ -665,17 +674,476 @@ def serve_bench(args, n_pool=24, n_requests=400, seed=5):
                       "method": "FP-BJ-CG L=4 symmetric, heuristic format per class, I=12", "slots": 8}))
 
 
+# Peaks of one MI355X used for the roofline (dense, no sparsity): HBM3E
+# bandwidth and the matrix-core rates of each operand format.
+PEAK_FLOPS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "fp8": 5.0e15}
+
+# The configured schedules of each batch workload: operand format, Jacobi
+# block size (0 = FP-CG), FP64 residual refresh period, FP64 refinement
+# steps, block-Jacobi form (0 Alg. 3 as printed, 2 its symmetric form).
+CONFIGURED = {
+    "c1": [dict(sched="fp64", L=0, refresh=0, refine=0, variant=0)],
+    "c2": [dict(sched="fp32", L=0, refresh=0, refine=0, variant=0),
+           dict(sched="bf16", L=0, refresh=0, refine=0, variant=0)],
+    "c3": [dict(sched="fp16", L=4, refresh=4, refine=0, variant=2),
+           dict(sched="fp16", L=8, refresh=4, refine=0, variant=2)],
+    "c4": [dict(sched="fp8", L=16, refresh=0, refine=1, variant=0)],
+    "paper": [dict(sched="fp16", L=8, refresh=0, refine=0, variant=2)],
+}
+# fixed iteration count where the workload states one (c1: 8)
+FIXED_ITERS = {"c1": 8}
+
+
+def work_model(B, Nbs, K, R, L, iters, sched, refresh=0, refine=0, elem=8):
+    """Algorithmic work of one launch over B channels: HBM bytes (inputs read,
+    outputs written), matrix-core flops in the operand format and FP64 flops.
+    Per channel: the Hermitian Gram 4 K (K+1) Nbs and matched filter
+    8 K Nbs R real flops; per solve and iteration 8 K^2 R for A p plus about
+    40 K R for the inner products and vector updates (and 8 K L R for z =
+    M_d r); the block-Jacobi setup about 8 K L^2; every FP64 refresh 8 K^2 R;
+    every refinement step 16 Nbs K R FP64 flops for H^H (y - H x) and one more
+    solve."""
+    gram = 4.0 * K * (K + 1) * Nbs + 8.0 * K * Nbs * R
+    solves = 1 + refine
+    cg = iters * R * (8.0 * K * K + 40.0 * K + (8.0 * K * L if L else 0.0)) + (8.0 * K * L * L if L else 0.0)
+    n_ref = (iters - 1) // refresh if refresh and iters > 0 else 0
+    f64 = solves * n_ref * R * 8.0 * K * K + refine * 16.0 * Nbs * K * R
+    low = gram + solves * cg
+    if sched == "fp64":
+        f64, low = f64 + low, 0.0
+    return {"bytes": algorithmic_bytes(B, Nbs, K, R, elem, refine), "lowp_flops": B * low, "fp64_flops": B * f64}
+
+
+def roofline_of(work, sched, kern_ms, traffic=None):
+    """The roof that binds (the largest time at peak among HBM, the operand
+    format's matrix cores and FP64) with the achieved rate on it."""
+    t = kern_ms * 1e-3
+    roofs = {"hbm": (work["bytes"] / (HBM_PEAK_GBS * 1e9), work["bytes"] / t / 1e9, HBM_PEAK_GBS, "GB/s")}
+    if work["lowp_flops"] > 0:
+        pk = PEAK_FLOPS[sched]
+        roofs["mfma_" + sched] = (work["lowp_flops"] / pk, work["lowp_flops"] / t / 1e12, pk / 1e12, "TFLOP/s")
+    if work["fp64_flops"] > 0:
+        pk = PEAK_FLOPS["fp64"]
+        roofs["mfma_fp64"] = (work["fp64_flops"] / pk, work["fp64_flops"] / t / 1e12, pk / 1e12, "TFLOP/s")
+    name = max(roofs, key=lambda k: roofs[k][0])
+    _, ach, peak, unit = roofs[name]
+    return {"bound": "hbm" if name == "hbm" else "mfma", "roof": name, "achieved": round(ach, 2), "peak": peak,
+            "unit": unit, "frac": round(ach / peak, 4), "traffic": traffic,
+            "roofs": {k: {"time_at_peak_us": round(v[0] * 1e6, 2), "achieved": round(v[1], 2), "peak": v[2],
+                          "unit": v[3], "frac": round(v[1] / v[2], 4)} for k, v in roofs.items()}}
+
+
+def _oracle_worker(task):
+    """One host process of the CPU baseline: FP64 CG (Alg. 2) of the oracle on
+    its chunk of channels, repeated for `seconds`, one BLAS thread."""
+    H, Y, s2, q, iters, seconds = task
+    from threadpoolctl import threadpool_limits
+
+    from oracle import detect as D
+
+    n, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        while True:
+            D.detect(H, Y, s2, q, iters, 0, D.FP64)
+            n += H.shape[0]
+            if time.perf_counter() - t0 >= seconds:
+                break
+    return n, time.perf_counter() - t0
+
+
+def cpu_oracle_baseline(wl, q, iters, R, seconds=8.0, chunk=32):
+    """The oracle's FP64 CG timed on the host: one process on one core, then
+    one process per available core (up to 16) each on its own chunk of
+    channels (complex64 inputs widened to complex128, as the GPU reads them)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    host = _host_cpu()
+    ncore = max(1, min(16, host["cores_available"] or 1))
+    B = wl.H.shape[0]
+
+    def task(i):
+        s0 = (i * chunk) % max(1, B - chunk)
+        h = wl.H[s0:s0 + chunk].astype(np.complex64).astype(np.complex128)
+        y = wl.Y[s0:s0 + chunk].astype(np.complex64).astype(np.complex128)
+        return h, y, wl.sigma2[s0:s0 + chunk], q, iters, seconds
+
+    n1, t1 = _oracle_worker(task(0))
+    res = {"single_core": {"value": round(n1 * R / t1, 1), "cores": 1, "seconds": round(t1, 2)}}
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=ncore, mp_context=ctx) as ex:
+        outs = list(ex.map(_oracle_worker, [task(i) for i in range(ncore)]))
+    n_all = sum(o[0] for o in outs)
+    t_all = max(o[1] for o in outs)
+    res["all_cores"] = {"value": round(n_all * R / t_all, 1), "cores": ncore, "seconds": round(t_all, 2)}
+    return res, host
+
+
+def graph_timed(fn, steps, warmup, idle):
+    """Capture one launch (fn(stream)) in a HIP graph, replay it `warmup`
+    times untimed, then `steps` times with HIP events around every replay on
+    the launch stream.  Returns (wall seconds of the timed replays, per-replay
+    milliseconds)."""
+    import torch
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn(side)                                      # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn(torch.cuda.current_stream())
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    time.sleep(idle)                                  # start from an idle board (clocks drop under load)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def profile_run(args):
+    """Short run for profilers: the launches of one schedule (--schedule, --L,
+    --iters, --refresh, --refine, --variant; 'auto' = the workload's first
+    configured schedule at its default iterations), in the launch form the
+    autotuner picks, then three plain 1 GiB device copies whose counter
+    readings scale the HBM byte counters.  Prints one JSON line."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+
+    c = W.CONFIGS[args.config]
+    B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
+    dev = torch.device("cuda:0")
+    cd = dict(CONFIGURED[args.config][0])
+    if args.schedule != "auto":
+        cd = dict(sched=args.schedule, L=0 if args.L == "auto" else int(args.L), refresh=args.refresh,
+                  refine=args.refine, variant=args.variant)
+    it = args.iters or FIXED_ITERS.get(args.config) or 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    H = (torch.randn(B, Nbs, K, dtype=torch.complex64, device=dev, generator=g) / math.sqrt(Nbs)).contiguous()
+    Y = torch.randn(B, Nbs, R, dtype=torch.complex64, device=dev, generator=g).contiguous()
+    s2 = torch.full((B,), W.sigma2_from_snr_db(c["snr_db"], Nbs, "paper"), dtype=torch.float64, device=dev)
+    ctx = fp.Context(0)
+    form = "fused"
+    if not args.no_tune:
+        form = ctx.autotune(B, Nbs, K, R, q, it, cd["L"], cd["sched"], cd["refresh"], cd["refine"], cd["variant"], reps=2)
+    out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
+           torch.empty((B,), dtype=torch.int32, device=dev))
+    fn = lambda st: fp.detect(H, Y, s2, q, it, cd["L"], cd["sched"], refresh_every=cd["refresh"],
+                              refine_steps=cd["refine"], variant=cd["variant"], ctx=ctx, out=out, stream=st)
+    wall, per = graph_timed(fn, args.steps, args.warmup, IDLE_S)
+    if args.kappa_profile:                           # the same launches with the kappa estimate
+        kap = torch.empty((B,), dtype=torch.float32, device=dev)
+        for _ in range(args.steps):
+            fp.detect(H, Y, s2, q, it, cd["L"], cd["sched"], refresh_every=cd["refresh"], variant=cd["variant"],
+                      ctx=ctx, out=out, kappa=kap)
+        torch.cuda.synchronize()
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # a plain copy of known size, to scale
+    b = torch.empty_like(a)                                     # the HBM byte counters
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("profile copy: 1 GiB read + 1 GiB write per copy, 3 copies")
+    print(json.dumps({"profile": True, "config": args.config, "schedule": cd["sched"], "L": cd["L"],
+                      "variant": cd["variant"], "refresh": cd["refresh"], "refine": cd["refine"], "iters": it,
+                      "launch_form": form, "kernel_ms_mean": float(np.mean(per)),
+                      "kernel_source_hash": kernel_source_hash()}))
+
+
+def batch_bench(args):
+    """One batch workload (default c3): the configured mixed-precision schedules
+    and FP64 CG on the same GPU, each at its BER-parity iteration count, timed
+    from warm graph replays; one JSON line."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+    import workload as W
+    from paper_2504_09820_amd import precision
+
+    c = W.CONFIGS[args.config]
+    B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
+    dev = torch.device("cuda:0")
+    io = np.complex128 if args.config == "c1" else np.complex64
+    tio = torch.complex128 if io == np.complex128 else torch.complex64
+    t0 = time.time()
+    wl = W.draw(B, Nbs, K, R, q, c["snr_db"], c["zeta"], c["zeta"], seed=2504_09820 * 10 + int(args.config[-1])
+                if args.config[-1].isdigit() else 2504_09820 * 10, normalization=c["normalization"])
+    log(f"workload {args.config}: B={B} Nbs={Nbs} K={K} R={R} Q={q} zeta={c['zeta']} snr={c['snr_db']} dB "
+        f"(drawn in {time.time() - t0:.1f} s)")
+    Hn = wl.H.astype(io)
+    H = torch.from_numpy(Hn).to(dev)
+    Y = torch.from_numpy(wl.Y.astype(io)).to(dev)
+    s2 = torch.from_numpy(wl.sigma2).to(dev)
+    tx = torch.from_numpy(wl.labels.astype(np.uint8)).to(dev)
+    ctx = fp.Context(0)
+
+    # ---------------------------------------------------------------- candidates
+    if args.schedule == "auto":
+        cands = [dict(d) for d in CONFIGURED[args.config]]
+    else:
+        Ls = [4, 8] if args.L == "auto" else [int(args.L)]
+        cands = [dict(sched=args.schedule, L=L, refresh=args.refresh, refine=args.refine,
+                      variant=args.variant if L else 0) for L in Ls if L == 0 or K % L == 0]
+    heur = {}
+    for cd in cands + [dict(L=0)]:
+        L = cd["L"]
+        if L in heur:
+            continue
+        kappa = precision.expected_kappa(H, Y, s2, L, sample=64, ctx=ctx)
+        fmt, ub = precision.choose_format(K, kappa, allow_fp8=False)
+        heur[L] = {"L": L, "expected_kappa": round(kappa, 3), "u_bound": ub, "format": fmt}
+        log(f"L={L}: E[kappa] = {kappa:.2f}, heuristic bound u < {ub:.3e} selects {fmt}")
+    for cd in cands:
+        cd["heuristic"] = heur[cd["L"]]["format"]
+
+    xo = torch.empty((B, K, R), dtype=tio, device=dev)
+    lo = torch.empty((B, K, R), dtype=torch.uint8, device=dev)
+    fo = torch.empty((B,), dtype=torch.int32, device=dev)
+
+    def launcher(cd, it):
+        return lambda st: fp.detect(H, Y, s2, q, it, cd["L"], cd["sched"], refresh_every=cd["refresh"],
+                                    refine_steps=cd["refine"], variant=cd["variant"], ctx=ctx, out=(xo, lo, fo),
+                                    stream=st)
+
+    def tune(cd, it):
+        if args.no_tune:
+            return "fused"
+        form = ctx.autotune(B, Nbs, K, R, q, it, cd["L"], cd["sched"], cd["refresh"], cd["refine"], cd["variant"],
+                            io="complex64" if io == np.complex64 else "complex128", reps=3)
+        log(f"  autotuned launch form for {cd['sched']} L={cd['L']} refresh={cd['refresh']}: {form}")
+        return form
+
+    # ---------------------------------------------------------------- BER parity at the 1e-3 operating point
+    # A slice of the same draw; other SNRs reuse its channels, symbols and
+    # noise realisation (common random numbers): Y = H X + n s.
+    nb = min(B, 4096)
+    Hs, ts = H[:nb], tx[:nb]
+    HX = torch.matmul(Hs.to(torch.complex128), torch.from_numpy(wl.X[:nb]).to(dev))
+    N0 = Y[:nb].to(torch.complex128) - HX
+    sig0 = float(wl.sigma2[0])
+
+    def inputs_at(snr_db):
+        s2_ = W.sigma2_from_snr_db(snr_db, Nbs, c["normalization"])
+        Ys_ = (HX + N0 * math.sqrt(s2_ / sig0)).to(tio)
+        return Ys_, torch.full((nb,), s2_, dtype=torch.float64, device=dev)
+
+    def ber_at(cd, it, snr_db):
+        Ys_, ss_ = inputs_at(snr_db)
+        _, lab, _ = fp.detect(Hs, Ys_, ss_, q, it, cd["L"], cd["sched"], refresh_every=cd["refresh"],
+                              refine_steps=cd["refine"], variant=cd["variant"], ctx=ctx)
+        return ber_of(lab, ts, q)
+
+    def crossing(points, target=1e-3):
+        """SNR where log10(BER) crosses target, by linear interpolation in dB."""
+        pts = sorted(points)
+        for (s0_, b0), (s1_, b1) in zip(pts, pts[1:]):
+            if b0 > target >= b1 and b1 > 0:
+                t = (math.log10(b0) - math.log10(target)) / (math.log10(b0) - math.log10(b1))
+                return s0_ + t * (s1_ - s0_)
+        return None
+
+    F64 = dict(sched="fp64", L=0, refresh=0, refine=0, variant=0)
+    itmax = 3 * K
+    fixed = FIXED_ITERS.get(args.config)
+    conv = {}
+    snr = float(c["snr_db"])
+    while snr <= 45.0:
+        conv[snr] = ber_at(F64, itmax, snr)
+        if conv[snr] <= 1e-3:
+            break
+        snr += 1.0
+    snr_op = crossing(list(conv.items())) or snr
+    berconv = ber_at(F64, itmax, snr_op)
+    I64 = args.iters64 or fixed
+    if not I64:
+        I64 = itmax
+        for it in range(2, itmax + 1):
+            if ber_at(F64, it, snr_op) <= berconv * 1.02:
+                I64 = it
+                break
+    ber64 = ber_at(F64, I64, snr_op)
+    log(f"BER 1e-3 operating point: converged FP64 crosses 1e-3 at {snr_op:.2f} dB (BER {berconv:.2e}); "
+        f"FP64 CG I64={I64} {ber64:.2e}")
+
+    def search(cd):
+        if args.iters or fixed:
+            return args.iters or fixed
+        for it in range(1, itmax + 1):
+            if ber_at(cd, it, snr_op) <= ber64 * 1.02:
+                return it
+        return itmax
+
+    heur_cd = None
+    hf = heur[cands[0]["L"]]["format"]
+    if args.schedule == "auto" and hf != "fp64" and all(cd["sched"] != hf for cd in cands):
+        heur_cd = dict(cands[0], sched=hf, refresh=0, refine=0)
+    for cd in cands + ([heur_cd] if heur_cd else []):
+        cd["iters"] = search(cd)
+        cd["form"] = tune(cd, cd["iters"])
+        cd["ber"] = ber_at(cd, cd["iters"], snr_op)
+        _, per = graph_timed(launcher(cd, cd["iters"]), 10, 3, 0.0)
+        cd["p50_ms"] = float(np.median(per))
+        log(f"  {cd['sched']} L={cd['L']} refresh={cd['refresh']} refine={cd['refine']} v{cd['variant']}: "
+            f"I={cd['iters']} BER {cd['ber']:.2e}, kernel p50 {cd['p50_ms']:.4f} ms ({cd['form']})")
+    best = min(cands, key=lambda d: d["p50_ms"])
+    form64 = tune(F64, I64)
+
+    # BER-vs-SNR gap at 1e-3 between the timed schedule and FP64 CG (and the converged solve)
+    grid = [round(snr_op + d, 2) for d in (-2.0, -1.0, 0.0, 1.0, 2.0)]
+    curves = {"converged": [], "fp64_cg": [], "mixed": []}
+    for sn in grid:
+        curves["converged"].append((sn, ber_at(F64, itmax, sn)))
+        curves["fp64_cg"].append((sn, ber_at(F64, I64, sn)))
+        curves["mixed"].append((sn, ber_at(best, best["iters"], sn)))
+    snr_at = {k: crossing(v) for k, v in curves.items()}
+    gap64 = None if None in (snr_at["mixed"], snr_at["fp64_cg"]) else snr_at["mixed"] - snr_at["fp64_cg"]
+    gapc = None if None in (snr_at["mixed"], snr_at["converged"]) else snr_at["mixed"] - snr_at["converged"]
+    log(f"SNR at BER 1e-3: converged {snr_at['converged']}, FP64 CG {snr_at['fp64_cg']}, {best['sched']} "
+        f"L={best['L']} {snr_at['mixed']}; gap vs FP64 CG {gap64} dB")
+
+    # ---------------------------------------------------------------- timed runs (warm graph replays)
+    wall_mp, per_mp = graph_timed(launcher(best, best["iters"]), args.steps, args.warmup, IDLE_S)
+    torch.cuda.synchronize()
+    x_mp = xo.clone()
+    ms_step = wall_mp / args.steps * 1e3
+    value = B * R / (wall_mp / args.steps)
+    log(f"{best['sched']} L={best['L']}: {ms_step:.4f} ms/step wall, kernel p50 {np.median(per_mp):.4f} ms, "
+        f"{value:.4e} detections/s")
+    steps64 = max(5, args.steps // 4)
+    wall_64, per_64 = graph_timed(launcher(F64, I64), steps64, 2, IDLE_S)
+    torch.cuda.synchronize()
+    x_64 = xo.clone()
+    value64 = B * R / (wall_64 / steps64)
+    log(f"fp64 CG: {wall_64 / steps64 * 1e3:.4f} ms/step, {value64:.4e} detections/s")
+    heur_line = None
+    if heur_cd:
+        wall_h, per_h = graph_timed(launcher(heur_cd, heur_cd["iters"]), max(5, args.steps // 4), 2, IDLE_S)
+        heur_line = {"schedule": heur_cd["sched"], "L": heur_cd["L"], "variant": heur_cd["variant"],
+                     "iters": heur_cd["iters"], "form": heur_cd["form"], "ber": heur_cd["ber"],
+                     "p50_ms": round(float(np.median(per_h)), 5),
+                     "value": round(B * R / (wall_h / max(5, args.steps // 4)), 1),
+                     "speedup_vs_fp64_cg": round((wall_64 / steps64) / (wall_h / max(5, args.steps // 4)), 3)}
+
+    # ---------------------------------------------------------------- roofline of the fused kernel
+    kern_ms = float(np.mean(per_mp))
+    work = work_model(B, Nbs, K, R, best["L"], best["iters"], best["sched"], best["refresh"], best["refine"],
+                      16 if io == np.complex128 else 8)
+    traffic = None
+    tf = traffic_file(args.config, best["sched"], best["L"], best["variant"], best["iters"])
+    if os.path.exists(tf):
+        try:
+            t = json.load(open(tf))
+            if t.get("kernel_source_hash") == kernel_source_hash() and t.get("refresh", 0) == best["refresh"]:
+                traffic = t.get("hbm_bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    roofline = roofline_of(work, best["sched"], kern_ms, traffic)
+    work64 = work_model(B, Nbs, K, R, 0, I64, "fp64", elem=16 if io == np.complex128 else 8)
+    roof64 = roofline_of(work64, "fp64", float(np.mean(per_64)))
+
+    # ---------------------------------------------------------------- CPU oracle baseline (and errors vs the FP64 oracle)
+    cpu = None
+    errs = None
+    if not args.no_cpu:
+        from oracle import detect as D
+
+        rates, host = cpu_oracle_baseline(wl, q, I64, R, seconds=args.cpu_seconds)
+        cpu = {"value": rates["all_cores"]["value"], "unit": "detections/s", "cores": rates["all_cores"]["cores"],
+               "kind": "oracle",
+               "sample": f"chunks of 32 channels x {R} RHS of the same workload, one per host process, "
+                         f"FP64 CG (Alg. 2) with I={I64}, numpy batched over the chunk, one BLAS thread per process, "
+                         f"each process repeating its chunk for ~{args.cpu_seconds:.0f} s",
+               "single_core": rates["single_core"], "host": host}
+        log(f"CPU oracle: {rates['all_cores']['value']:.1f} detections/s on {rates['all_cores']['cores']} cores, "
+            f"{rates['single_core']['value']:.1f} on one")
+        # each timed result against the FP64 oracle on sampled channels: the
+        # exact LMMSE solution (Cholesky) and FP64 CG at the same I
+        smp = np.linspace(0, B - 1, 16).astype(np.int64)
+        h = wl.H[smp].astype(io).astype(np.complex128)
+        y = wl.Y[smp].astype(io).astype(np.complex128)
+        A_, b_ = D.gram(h, y, wl.sigma2[smp])
+        xs = D.lmmse(A_, b_)
+        cg64 = D.detect(h, y, wl.sigma2[smp], q, I64, 0, D.FP64).xhat
+
+        def rel(x, ref):
+            x = x.cpu().numpy()[smp].astype(np.complex128)
+            e = np.linalg.norm(x - ref, axis=-2) / np.linalg.norm(ref, axis=-2)
+            return {"median": float(np.median(e)), "max": float(np.max(e))}
+
+        errs = {"channels": int(smp.size), "mixed_vs_lmmse": rel(x_mp, xs), "fp64_cg_vs_lmmse": rel(x_64, xs),
+                "fp64_cg_vs_oracle_fp64_cg": rel(x_64, cg64)}
+        log(f"errors vs the FP64 oracle: {errs}")
+
+    out = {
+        "metric": "detections/sec (FP-BJ-CG vs FP64 CG) at BER parity; p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "detections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8": "f8e4m3"}[best["sched"]],
+        "data": "synthetic (seeded Kronecker-correlated Rayleigh channels, uniform Gray QAM, AWGN)",
+        "config": {"workload": f"{args.config}: Nbs={Nbs} K={K} R={R} B={B} zeta={c['zeta']} {q}-QAM "
+                               f"SNR={c['snr_db']}dB", "method": "FP-BJ-CG" if best["L"] else "FP-CG",
+                   "schedule": best["sched"], "block_L": best["L"], "variant": best["variant"],
+                   "refresh_every": best["refresh"], "refine_steps": best["refine"], "iters": best["iters"],
+                   "launch_form": best["form"], "fp64_iters": I64, "fp64_launch_form": form64,
+                   "io": "complex64" if io == np.complex64 else "complex128", "timing": "warm HIP graph replays"},
+        "latency_ms": {"p50": round(float(np.median(per_mp)), 5), "p99": round(float(np.quantile(per_mp, 0.99)), 5),
+                       "kernel_mean": round(kern_ms, 5)},
+        "algorithmic_bytes_per_launch": work["bytes"],
+        "fp64_cg": {"value": round(value64, 1), "ms_per_step": round(wall_64 / steps64 * 1e3, 5),
+                    "p50_ms": round(float(np.median(per_64)), 5), "p99_ms": round(float(np.quantile(per_64, 0.99)), 5),
+                    "roofline": roof64},
+        "speedup_vs_fp64_cg": round(value / value64, 3),
+        "ber": {"operating_snr_db": round(snr_op, 3), "bits": int(nb * K * R * math.log2(q)),
+                "converged_fp64": berconv, "fp64_cg": ber64, "mixed": best["ber"],
+                "snr_db_at_1e-3": {k: (None if v is None else round(v, 3)) for k, v in snr_at.items()},
+                "gap_db_vs_fp64_cg": None if gap64 is None else round(gap64, 3),
+                "gap_db_vs_converged": None if gapc is None else round(gapc, 3)},
+        "candidates": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in cd.items()} for cd in cands],
+        "heuristic": {"picks": list(heur.values()), "timed_pick": heur_line},
+        "error_vs_fp64_oracle": errs,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2")
-    ap.add_argument("--schedule", default="auto", help="operand format, or 'auto' for the precision heuristic")
+    ap.add_argument("--config", default="c3", help="c1, c2, c3 (default), c4 or paper")
+    ap.add_argument("--schedule", default="auto",
+                    help="operand format, or 'auto' for the workload's configured schedules (the heuristic's pick "
+                         "is timed beside them)")
     ap.add_argument("--L", default="auto", help="Jacobi block size (0 = FP-CG), or 'auto' for the faster of 4 and 8")
     ap.add_argument("--variant", type=int, default=2, help="block-Jacobi form (0 Alg. 3 as printed, 1 textbook, 2 symmetric)")
     ap.add_argument("--iters", type=int, default=0, help="mixed-schedule iterations (0 = BER-parity search)")
     ap.add_argument("--iters64", type=int, default=0, help="FP64 iterations (0 = BER-parity search)")
+    ap.add_argument("--refresh", type=int, default=0, help="FP64 refresh period (explicit --schedule only)")
+    ap.add_argument("--refine", type=int, default=0, help="FP64 refinement steps (explicit --schedule only)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-form autotuner (fused, default waves)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="seconds of oracle work per host process")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: the given schedule, L and iterations only, plus a 1 GiB copy")
@@ -724,239 +1192,10 @@ def main():
         print(json.dumps({"error": msg, "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import torch
-
-    import paper_2504_09820_amd as fp
-    import workload as W
-    from paper_2504_09820_amd import precision
-
-    c = W.CONFIGS[args.config]
-    B, Nbs, K, R, q = c["B"], c["Nbs"], c["K"], c["R"], c["q"]
-    dev = torch.device("cuda:0")
-    t0 = time.time()
-    wl = W.draw(B, Nbs, K, R, q, c["snr_db"], c["zeta"], c["zeta"], seed=2504_09820 * 10 + int(args.config[-1]),
-                normalization=c["normalization"])
-    log(f"workload {args.config}: B={B} Nbs={Nbs} K={K} R={R} Q={q} zeta={c['zeta']} snr={c['snr_db']} dB "
-        f"(drawn in {time.time() - t0:.1f} s)")
-    H64 = wl.H.astype(np.complex64)
-    H = torch.from_numpy(H64).to(dev)
-    Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
-    s2 = torch.from_numpy(wl.sigma2).to(dev)
-    tx = torch.from_numpy(wl.labels.astype(np.uint8)).to(dev)
-    ctx = fp.Context(0)
-    stream = torch.cuda.current_stream(dev)
-    variant = args.variant
-
-    # ------------------------------------------------------------ candidates (format by the heuristic)
-    Ls = [4, 8] if args.L == "auto" else [int(args.L)]
-    Ls = [L for L in Ls if L == 0 or K % L == 0]
-    cands = []
-    for L in Ls:
-        kappa = precision.expected_kappa(H64, wl.sigma2, L, sample=64)
-        fmt, ub = precision.choose_format(K, kappa, allow_fp8=False)
-        sched = fmt if args.schedule == "auto" else args.schedule
-        log(f"L={L}: E[kappa] = {kappa:.2f}, heuristic bound u < {ub:.3e} selects {fmt}; running {sched}")
-        cands.append({"L": L, "kappa": kappa, "u_bound": ub, "heuristic": fmt, "sched": sched})
-
-    xo = torch.empty((B, K, R), dtype=torch.complex64, device=dev)
-    lo = torch.empty((B, K, R), dtype=torch.uint8, device=dev)
-    fo = torch.empty((B,), dtype=torch.int32, device=dev)
-
-    def run(s, it, LL, v, steps, warmup, idle=0.0):
-        torch.cuda.synchronize()
-        time.sleep(idle)                             # start from an idle board (clocks drop under load)
-        for _ in range(warmup):
-            fp.detect(H, Y, s2, q, it, LL, s, variant=v, ctx=ctx, out=(xo, lo, fo), stream=stream)
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        t_start = time.perf_counter()
-        for e0, e1 in ev:
-            e0.record(stream)
-            fp.detect(H, Y, s2, q, it, LL, s, variant=v, ctx=ctx, out=(xo, lo, fo), stream=stream)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t_start
-        per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])   # ms, HIP events on the launch stream
-        return wall, per
-
     if args.profile:
-        cd = cands[0]
-        it = args.iters or 11
-        wall, per = run(cd["sched"], it, cd["L"], variant, args.steps, args.warmup, idle=IDLE_S)
-        if args.kappa_profile:                       # the same launches with the kappa estimate
-            kap = torch.empty((B,), dtype=torch.float32, device=dev)
-            for _ in range(args.steps):
-                fp.detect(H, Y, s2, q, it, cd["L"], cd["sched"], variant=variant, ctx=ctx, out=(xo, lo, fo),
-                          stream=stream, kappa=kap)
-            torch.cuda.synchronize()
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # a plain copy of known size, to scale
-        b = torch.empty_like(a)                                     # the HBM byte counters
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("profile copy: 1 GiB read + 1 GiB write per copy, 3 copies")
-        print(json.dumps({"profile": True, "schedule": cd["sched"], "L": cd["L"], "variant": variant, "iters": it,
-                          "kernel_ms_mean": float(np.mean(per)), "kernel_source_hash": kernel_source_hash()}))
+        profile_run(args)
         return
-
-    # ------------------------------------------------------------ BER parity at the 1e-3 operating point
-    # A 4096-channel slice of the same draw; other SNRs reuse its channels,
-    # symbols and noise realisation (common random numbers): Y = H X + n s.
-    nb = min(B, 4096)
-    Hs, ts = H[:nb], tx[:nb]
-    HX = torch.matmul(Hs.to(torch.complex128), torch.from_numpy(wl.X[:nb]).to(dev))
-    N0 = Y[:nb].to(torch.complex128) - HX
-    sig0 = float(wl.sigma2[0])
-
-    def inputs_at(snr_db):
-        s2_ = W.sigma2_from_snr_db(snr_db, Nbs, c["normalization"])
-        Ys_ = (HX + N0 * math.sqrt(s2_ / sig0)).to(torch.complex64)
-        return Ys_, torch.full((nb,), s2_, dtype=torch.float64, device=dev)
-
-    def ber_at(s, it, LL, v, snr_db):
-        Ys_, ss_ = inputs_at(snr_db)
-        _, lab, _ = fp.detect(Hs, Ys_, ss_, q, it, LL, s, variant=v, ctx=ctx)
-        return ber_of(lab, ts, q)
-
-    def crossing(points, target=1e-3):
-        """SNR where log10(BER) crosses target, by linear interpolation in dB."""
-        pts = sorted(points)
-        for (s0, b0), (s1, b1) in zip(pts, pts[1:]):
-            if b0 > target >= b1 and b1 > 0:
-                t = (math.log10(b0) - math.log10(target)) / (math.log10(b0) - math.log10(b1))
-                return s0 + t * (s1 - s0)
-        return None
-
-    conv = {}
-    snr = float(c["snr_db"])
-    while snr <= 45.0:
-        conv[snr] = ber_at("fp64", 3 * K, 0, 0, snr)
-        if conv[snr] <= 1e-3:
-            break
-        snr += 1.0
-    snr_op = crossing(list(conv.items())) or snr
-    berconv = ber_at("fp64", 3 * K, 0, 0, snr_op)
-    I64 = args.iters64
-    if not I64:
-        I64 = 3 * K
-        for it in range(2, 3 * K + 1):
-            if ber_at("fp64", it, 0, 0, snr_op) <= berconv * 1.02:
-                I64 = it
-                break
-    ber64 = ber_at("fp64", I64, 0, 0, snr_op)
-    log(f"BER 1e-3 operating point: converged FP64 crosses 1e-3 at {snr_op:.2f} dB (BER {berconv:.2e}); "
-        f"FP64 CG I64={I64} {ber64:.2e}")
-    for cd in cands:
-        imp = args.iters
-        if not imp:
-            imp = 3 * K
-            for it in range(1, 3 * K + 1):
-                if ber_at(cd["sched"], it, cd["L"], variant, snr_op) <= ber64 * 1.02:
-                    imp = it
-                    break
-        cd["iters"] = imp
-        cd["ber"] = ber_at(cd["sched"], imp, cd["L"], variant, snr_op)
-        _, per = run(cd["sched"], imp, cd["L"], variant, 10, 3)
-        cd["p50_ms"] = float(np.median(per))
-        log(f"  {cd['sched']} L={cd['L']} v{variant}: Imp={imp} BER {cd['ber']:.2e}, kernel p50 {cd['p50_ms']:.4f} ms")
-    best = min(cands, key=lambda d: d["p50_ms"])
-    sched, L, Imp = best["sched"], best["L"], best["iters"]
-
-    # BER-vs-SNR gap at 1e-3 between the timed schedule and FP64 CG (and the converged solve)
-    grid = [round(snr_op + d, 2) for d in (-2.0, -1.0, 0.0, 1.0, 2.0)]
-    curves = {"converged": [], "fp64_cg": [], "mixed": []}
-    for sn in grid:
-        curves["converged"].append((sn, ber_at("fp64", 3 * K, 0, 0, sn)))
-        curves["fp64_cg"].append((sn, ber_at("fp64", I64, 0, 0, sn)))
-        curves["mixed"].append((sn, ber_at(sched, Imp, L, variant, sn)))
-    snr_at = {k: crossing(v) for k, v in curves.items()}
-    gap64 = None if None in (snr_at["mixed"], snr_at["fp64_cg"]) else snr_at["mixed"] - snr_at["fp64_cg"]
-    gapc = None if None in (snr_at["mixed"], snr_at["converged"]) else snr_at["mixed"] - snr_at["converged"]
-    log(f"SNR at BER 1e-3: converged {snr_at['converged']}, FP64 CG {snr_at['fp64_cg']}, {sched} L={L} "
-        f"{snr_at['mixed']}; gap vs FP64 CG {gap64} dB")
-
-    # ------------------------------------------------------------ timed runs
-    wall_mp, per_mp = run(sched, Imp, L, variant, args.steps, args.warmup, idle=IDLE_S)
-    ms_step = wall_mp / args.steps * 1e3
-    value = B * R / (wall_mp / args.steps)
-    log(f"{sched} L={L}: {ms_step:.4f} ms/step wall, kernel p50 {np.median(per_mp):.4f} ms, {value:.4e} detections/s")
-    steps64 = max(5, args.steps // 5)
-    wall_64, per_64 = run("fp64", I64, 0, 0, steps64, 2, idle=IDLE_S)
-    value64 = B * R / (wall_64 / steps64)
-    log(f"fp64 CG: {wall_64 / steps64 * 1e3:.4f} ms/step, {value64:.4e} detections/s")
-
-    # ------------------------------------------------------------ roofline of the fused kernel
-    kern_ms = float(np.mean(per_mp))
-    nbytes = algorithmic_bytes(B, Nbs, K, R, 8)
-    achieved = nbytes / (kern_ms * 1e-3) / 1e9
-    traffic = None
-    tf = traffic_file(args.config, sched, L, variant, Imp)
-    if os.path.exists(tf):
-        try:
-            t = json.load(open(tf))
-            if t.get("kernel_source_hash") == kernel_source_hash():
-                traffic = t.get("hbm_bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
-
-    # ------------------------------------------------------------ CPU oracle baseline
-    cpu = None
-    if not args.no_cpu:
-        from threadpoolctl import threadpool_limits
-
-        from oracle import detect as D
-
-        # chunks of 256 channels, cycling over the batch, until ~10 s of CPU time; one thread
-        nsamp, dt, s0 = 0, 0.0, 0
-        with threadpool_limits(limits=1):
-            while dt < 10.0:
-                e = min(B, s0 + 256)
-                h = wl.H[s0:e].astype(np.complex64).astype(np.complex128)
-                y = wl.Y[s0:e].astype(np.complex64).astype(np.complex128)
-                t1 = time.perf_counter()
-                D.detect(h, y, wl.sigma2[s0:e], q, I64, 0, D.FP64)
-                dt += time.perf_counter() - t1
-                nsamp += e - s0
-                s0 = 0 if e == B else e
-        cpu = {"value": round(nsamp * R / dt, 1), "unit": "detections/s", "cores": 1, "kind": "oracle",
-               "sample": f"{nsamp} channels x {R} RHS of the same workload (chunks of 256, cycling over the batch), "
-                         f"FP64 CG (Alg. 2) with I={I64}, numpy batched over channels, one thread ({dt:.1f} s)",
-               "host": _host_cpu()}
-
-    out = {
-        "metric": "detections/sec (FP-BJ-CG vs FP64 CG) at BER parity; p50/p99 latency",
-        "value": round(value, 1),
-        "unit": "detections/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8": "f8e4m3"}[sched],
-        "data": "synthetic (seeded Kronecker-correlated Rayleigh channels, uniform Gray 64-QAM, AWGN)",
-        "config": {"workload": f"{args.config}: Nbs={Nbs} K={K} R={R} B={B} zeta={c['zeta']} {q}-QAM "
-                               f"SNR={c['snr_db']}dB", "method": "FP-BJ-CG" if L else "FP-CG", "schedule": sched,
-                   "block_L": L, "variant": variant, "iters": Imp, "fp64_iters": I64, "io": "complex64"},
-        "latency_ms": {"p50": round(float(np.median(per_mp)), 5), "p99": round(float(np.quantile(per_mp, 0.99)), 5),
-                       "kernel_mean": round(kern_ms, 5)},
-        "algorithmic_bytes_per_launch": nbytes,
-        "fp64_cg": {"value": round(value64, 1), "ms_per_step": round(wall_64 / steps64 * 1e3, 5),
-                    "p50_ms": round(float(np.median(per_64)), 5)},
-        "speedup_vs_fp64_cg": round(value / value64, 3),
-        "ber": {"operating_snr_db": round(snr_op, 3), "bits": int(nb * K * R * math.log2(q)),
-                "converged_fp64": berconv, "fp64_cg": ber64, "fp_bj_cg": best["ber"],
-                "snr_db_at_1e-3": {k: (None if v is None else round(v, 3)) for k, v in snr_at.items()},
-                "gap_db_vs_fp64_cg": None if gap64 is None else round(gap64, 3),
-                "gap_db_vs_converged": None if gapc is None else round(gapc, 3)},
-        "heuristic": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in cd.items()} for cd in cands],
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out))
+    batch_bench(args)
 
 
 if __name__ == "__main__":

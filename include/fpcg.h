@@ -103,28 +103,70 @@ typedef struct fpcg_ctx fpcg_ctx;
 
 /* Create a context on HIP device `device`.  `hbm_budget` bounds the device
  * memory the serving queue may hold for in-flight requests (0 = 80 % of the
- * free memory at creation).  Returns FPCG_E_DEVICE if the device is absent. */
-fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out);
+ * free memory at creation).  `tune_table`: NULL, or a table persisted from
+ * fpcg_tune_table (launch forms fpcg_autotune chose per shape class and
+ * expected condition numbers per workload class), loaded into the context;
+ * FPCG_E_INVAL if it does not parse (checked before any device call).
+ * Returns FPCG_E_DEVICE if the device is absent. */
+fpcg_status fpcg_create(int32_t device, size_t hbm_budget, const char* tune_table, fpcg_ctx** out);
+
+/* The context's table as NUL-terminated JSON:
+ *   {"version": 1,
+ *    "forms": [{"KP": .., "fmt": .., "L": .., "split": .., "refresh": .., "c64": .., "multi": .., "form": ..}, ...],
+ *    "kappa": [{"Nbs": .., "K": .., "L": .., "kappa": ..}, ...]}
+ * (forms: padded K, operand format, block size, symmetric form, refresh on,
+ * complex64 I/O, several blocks of received vectors -> the launch form of
+ * fpcg_set_launch_form).  *len (may be NULL) receives the bytes needed,
+ * terminator included; buf = NULL only queries the length; FPCG_E_INVAL if
+ * cap is too small.  Host only. */
+fpcg_status fpcg_tune_table(const fpcg_ctx* ctx, char* buf, size_t cap, size_t* len);
+
+/* Expected condition number E{kappa} of the iteration matrix of a workload
+ * class (Nbs, K, block_L): A = H^H H + sigma^2 I for block_L = 0, the
+ * block-Jacobi preconditioned matrix of eq. heuristic_bj otherwise.  The
+ * footnote to eq. heuristic allows the expectation in place of each
+ * channel's kappa.  fpcg_set_kappa records a known value;
+ * fpcg_expected_kappa estimates it on the device: n_sample channels spread
+ * evenly over the batch (H, Y, sigma2 as fpcg_detect, device memory) are
+ * gathered and solved with FP64 CG for min(K, 32) steps with the kappa output
+ * of fpcg_detect_ex, and *kappa receives the mean of the estimates (a lower
+ * estimate of each channel's kappa, exact in exact arithmetic when K <= 32).
+ * Both record the value in the context for the NULL schedule of
+ * fpcg_detect.  fpcg_expected_kappa allocates and frees its own device
+ * buffers and synchronises `stream`; FPCG_E_INVAL for bad sizes or NULL
+ * pointers, or when no sampled channel gives an estimate. */
+fpcg_status fpcg_set_kappa(fpcg_ctx* ctx, int32_t Nbs, int32_t K, int32_t block_L, double kappa);
+fpcg_status fpcg_expected_kappa(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                                const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                                int32_t block_L, int32_t n_sample, double* kappa);
 
 /* Waits for the context's own streams, then frees everything it owns. */
 void fpcg_destroy(fpcg_ctx* ctx);
 
-/* Launch form of fpcg_detect for channels one wave solves (padded K <= 32)
- * without refinement; larger K and refinement always use the fused form.
+/* Launch form of fpcg_detect.
  *   FPCG_LAUNCH_AUTO       (default) the form fpcg_autotune chose for the
- *                          launch's shape class, else the fused form;
+ *                          launch's shape class, else the fused form with
+ *                          the default waves per channel;
  *   FPCG_LAUNCH_FUSED      one workgroup per channel doing every step;
- *   FPCG_LAUNCH_PIPELINED  persistent two-wave workgroups, one wave forming
+ *   FPCG_LAUNCH_PIPELINED  (one-wave channels, padded K <= 32, no refinement)
+ *                          persistent two-wave workgroups, one wave forming
  *                          the Gram and matched filter of the next channel
  *                          while the other solves the current one from the
  *                          other half of a double buffer in LDS.
- * Both forms run the same per-channel arithmetic in the same order, so their
- * results are bitwise identical; only the schedule of work differs.
- * FPCG_E_INVAL for a NULL context or an unknown form. */
+ * The fused form may carry a wave count per channel,
+ *   FPCG_LAUNCH_FUSED | (nw << FPCG_LAUNCH_WAVES_SHIFT), nw in {1, 2, 4},
+ * which runs the workgroup of nw waves where that count is built for the
+ * launch's shape class (each wave then holds K/(4 nw) entries of every
+ * iterate per lane, so a Jacobi block must fit them), else the default count.
+ * Forms and wave counts run the same per-channel algorithm; the fused and
+ * pipelined forms of one wave count are bitwise identical, and other wave
+ * counts differ only in the order of the Gram's and the inner products'
+ * partial sums.  FPCG_E_INVAL for a NULL context or an unknown form. */
 enum { FPCG_LAUNCH_AUTO = 0, FPCG_LAUNCH_FUSED = 1, FPCG_LAUNCH_PIPELINED = 2 };
+#define FPCG_LAUNCH_WAVES_SHIFT 8
 fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form);
 
-/* Autotuner: times every launch form built for the shape class of these
+/* Autotuner: times every launch form (and wave count) built for the shape class of these
  * arguments (padded K, operand format, block size and form, refresh on/off,
  * I/O type, one or several blocks of received vectors) on synthetic inputs
  * of this size, `reps` interleaved launches each (1..1000), and records the
@@ -143,7 +185,8 @@ const char* fpcg_last_error(void);
 
 /* Host-only validation of a detect() configuration (no device needed).
  * Returns FPCG_OK, FPCG_E_INVAL or FPCG_E_UNSUPPORTED exactly as
- * fpcg_detect would for the same sizes and schedule. */
+ * fpcg_detect would for the same sizes and schedule (sched = NULL checks the
+ * sizes with the all-FP64 schedule). */
 fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam_order,
                        int32_t iters, int32_t block_L, const fpcg_schedule* sched);
 
@@ -162,7 +205,16 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  *   65 <= K <= 128 is built for fp8, fp16 and bf16 operands, left block-Jacobi
  *   forms (variant 0 or 1) and no FP64 refresh; with fp8 also with FP64
  *   refinement.  Other combinations return FPCG_E_UNSUPPORTED.
- *   sched = NULL means the all-FP64 schedule.
+ *   sched = NULL selects the schedule by the precision heuristic (eq.
+ *   heuristic for block_L = 0, eq. heuristic_bj otherwise): with kappa the
+ *   expected condition number the context holds for (Nbs, K, block_L)
+ *   (fpcg_expected_kappa, fpcg_set_kappa, or the tune table of
+ *   fpcg_create), the cheapest format whose unit roundoff is below
+ *   1 / (K^1.5 sqrt(kappa)) (fpcg_select_precision with fp8 allowed; the next
+ *   more precise built format where that one is not built for the shape),
+ *   operands of the Gram and of A p in it, u_IP = u_W = FP32 (FP64 for the
+ *   FP64 format), no refresh or refinement, the symmetric block-Jacobi form.
+ *   FPCG_E_INVAL if the context holds no kappa for that class.
  *   flags may be NULL.
  */
 fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream,
@@ -208,6 +260,21 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
                            const fpcg_schedule* sched,
                            void* xhat, uint8_t* labels, uint32_t* flags,
                            const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain);
+
+/* Step a0-a1 on its own (Sec. II, eq. inversion): the Gram A = H^H H +
+ * sigma^2 I and the matched filter B = H^H Y of every channel, formed exactly
+ * as fpcg_detect forms them for `sched` (H and Y rounded to sched->gram_op,
+ * per-channel / per-column power-of-two scales for fp8, products accumulated
+ * on the matrix cores, sigma^2 added to the rounded diagonal), written in u_W:
+ * A_out (B, K, K) and B_out (B, K, R), interleaved complex64 for u_W = F32,
+ * complex128 for F64, device memory.  A is Hermitian (the upper triangle is
+ * formed, the lower one written as its conjugate).  flags (may be NULL)
+ * receives the flags of this step (NONFINITE, FP8_SAT).  refresh, refinement
+ * and variant of `sched` are ignored.  Errors as fpcg_detect; sched must not
+ * be NULL. */
+fpcg_status fpcg_gram(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                      const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                      const fpcg_schedule* sched, void* A_out, void* B_out, uint32_t* flags);
 
 /* Soft output for a channel decoder (Sec. V evaluates the detector in a coded
  * link, Fig. coding): max-log LLRs of each estimated symbol.  The model of

@@ -17,7 +17,7 @@ from typing import Optional
 
 __all__ = [
     "FMT", "FLAGS", "Schedule", "schedule", "Context", "FpcgError", "lib", "library_path",
-    "detect", "check", "slice_qam", "demap_maxlog", "round_operand", "select_precision", "Server",
+    "detect", "check", "gram", "slice_qam", "demap_maxlog", "round_operand", "select_precision", "Server",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -76,8 +76,15 @@ def lib():
     st = ctypes.c_int32
     vp = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64
-    L.fpcg_create.argtypes = [i32, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.fpcg_create.argtypes = [i32, ctypes.c_size_t, ctypes.c_char_p, ctypes.POINTER(vp)]
     L.fpcg_create.restype = st
+    L.fpcg_tune_table.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    L.fpcg_tune_table.restype = st
+    L.fpcg_set_kappa.argtypes = [vp, i32, i32, i32, ctypes.c_double]
+    L.fpcg_set_kappa.restype = st
+    L.fpcg_expected_kappa.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32,
+                                      ctypes.POINTER(ctypes.c_double)]
+    L.fpcg_expected_kappa.restype = st
     L.fpcg_destroy.argtypes = [vp]
     L.fpcg_destroy.restype = None
     L.fpcg_set_launch_form.argtypes = [vp, i32]
@@ -100,6 +107,8 @@ def lib():
     L.fpcg_detect_ex.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule),
                                  vp, vp, vp, vp, i64, vp, vp]
     L.fpcg_detect_ex.restype = st
+    L.fpcg_gram.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, ctypes.POINTER(Schedule), vp, vp, vp]
+    L.fpcg_gram.restype = st
     L.fpcg_demap_maxlog.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp]
     L.fpcg_demap_maxlog.restype = st
     L.fpcg_demap_maxlog_i8.argtypes = [vp, i64, i32, vp, i32, vp, i32, ctypes.c_float, vp]
@@ -144,13 +153,72 @@ def select_precision(N: int, kappa: float, allow_fp8: bool = True):
     return FMT_NAME[f.value], u.value
 
 
+LAUNCH_WAVES_SHIFT = 8
+
+
+def _form_code(form: str) -> int:
+    base = {"auto": 0, "fused": 1, "pipelined": 2}
+    if form in base:
+        return base[form]
+    if form.startswith("fused-w") and form[7:] in ("1", "2", "4"):
+        return 1 | (int(form[7:]) << LAUNCH_WAVES_SHIFT)
+    raise ValueError(f"unknown launch form {form!r}")
+
+
+def _form_name(code: int) -> str:
+    nw = code >> LAUNCH_WAVES_SHIFT
+    base = {0: "auto", 1: "fused", 2: "pipelined"}[code & ((1 << LAUNCH_WAVES_SHIFT) - 1)]
+    return f"{base}-w{nw}" if nw else base
+
+
 class Context:
     """A device context (fpcg_create / fpcg_destroy)."""
 
-    def __init__(self, device: int = 0, hbm_budget: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tune_table: "str | dict | None" = None):
+        """tune_table: a table from tune_table() (JSON text or its parsed dict)
+        with launch forms and expected condition numbers to start from."""
+        import json
+
         self._h = ctypes.c_void_p()
-        _check(lib().fpcg_create(device, hbm_budget, ctypes.byref(self._h)))
+        tt = None
+        if tune_table is not None:
+            tt = (json.dumps(tune_table) if isinstance(tune_table, dict) else str(tune_table)).encode()
+        _check(lib().fpcg_create(device, hbm_budget, tt, ctypes.byref(self._h)))
         self.device = device
+
+    def tune_table(self) -> str:
+        """The context's launch forms and expected condition numbers as JSON
+        (fpcg_tune_table), to persist and pass to a later Context."""
+        n = ctypes.c_size_t()
+        _check(lib().fpcg_tune_table(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().fpcg_tune_table(self._h, buf, n.value, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def set_kappa(self, Nbs: int, K: int, L: int, kappa: float):
+        """Record E{kappa} of the workload class (Nbs, K, L) for the heuristic
+        schedule (detect with schedule_=None)."""
+        _check(lib().fpcg_set_kappa(self._h, Nbs, K, L, float(kappa)))
+
+    def expected_kappa(self, H, Y, sigma2, L: int = 0, sample: int = 64, stream=None) -> float:
+        """E{kappa} of the iteration matrix estimated on the device from
+        `sample` channels of the batch (fpcg_expected_kappa); also recorded in
+        the context for the heuristic schedule."""
+        import torch
+
+        if not (H.is_cuda and Y.is_cuda and sigma2.is_cuda) or H.dtype != Y.dtype or \
+                H.dtype not in (torch.complex64, torch.complex128) or sigma2.dtype != torch.float64:
+            raise TypeError("H, Y: complex64/complex128 CUDA tensors of one dtype; sigma2: float64 CUDA tensor")
+        H, Y, sigma2 = H.contiguous(), Y.contiguous(), sigma2.contiguous()
+        B, Nbs, K = H.shape
+        if Y.dim() != 3 or Y.shape[:2] != (B, Nbs) or sigma2.shape != (B,):
+            raise ValueError("shape mismatch between H, Y and sigma2")
+        out = ctypes.c_double()
+        _check(lib().fpcg_expected_kappa(self._h, _stream_handle(stream, H.device), B, Nbs, K, Y.shape[2],
+                                         ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                         1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
+                                         L, sample, ctypes.byref(out)))
+        return out.value
 
     @property
     def handle(self):
@@ -167,13 +235,14 @@ class Context:
         out = ctypes.c_int32()
         _check(lib().fpcg_autotune(self._h, ctypes.c_void_p(s.cuda_stream), B, Nbs, K, R, 1 if io == "complex64" else 0,
                                    qam, iters, L, ctypes.byref(sched), reps, ctypes.byref(out)))
-        return {1: "fused", 2: "pipelined"}[out.value]
+        return _form_name(out.value)
 
     def set_launch_form(self, form: str = "auto"):
-        """"auto" (the library's choice), "fused" (one workgroup per channel) or
-        "pipelined" (two-wave pipelined form where built); results are bitwise
-        the same."""
-        _check(lib().fpcg_set_launch_form(self._h, {"auto": 0, "fused": 1, "pipelined": 2}[form]))
+        """"auto" (the library's choice), "fused" (one workgroup per channel),
+        "fused-w1" / "fused-w2" / "fused-w4" (the fused form with that many
+        waves per channel where built for a launch's shape) or "pipelined"
+        (two-wave pipelined form where built)."""
+        _check(lib().fpcg_set_launch_form(self._h, _form_code(form)))
 
     def close(self):
         if self._h:
@@ -234,7 +303,7 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     if isinstance(schedule_, str):
         sched = schedule(schedule_, refresh_every, refine_steps, variant)
     else:
-        sched = schedule_
+        sched = schedule_                       # a Schedule, or None: the heuristic's (fpcg_detect)
     if H.dtype not in (torch.complex64, torch.complex128) or Y.dtype != H.dtype:
         raise TypeError("H and Y must both be complex64 or both complex128")
     if not (H.is_cuda and Y.is_cuda and sigma2.is_cuda):
@@ -273,7 +342,7 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         _check(lib().fpcg_detect_ex(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                                     ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                                     1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
-                                    qam, iters, L, ctypes.byref(sched),
+                                    qam, iters, L, ctypes.byref(sched) if sched is not None else None,
                                     ctypes.c_void_p(xhat.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
                                     ctypes.c_void_p(flags.data_ptr()),
                                     ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
@@ -284,10 +353,40 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     _check(lib().fpcg_detect(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                              ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                              1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
-                             qam, iters, L, ctypes.byref(sched),
+                             qam, iters, L, ctypes.byref(sched) if sched is not None else None,
                              ctypes.c_void_p(xhat.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
                              ctypes.c_void_p(flags.data_ptr())))
     return xhat, labels, flags
+
+
+def gram(H, Y, sigma2, schedule_: "str | Schedule" = "fp64", ctx: Optional[Context] = None, stream=None):
+    """The Gram A = H^H H + sigma^2 I (B, K, K) and matched filter H^H Y
+    (B, K, R) as the detector forms them for the schedule (fpcg_gram), in u_W:
+    complex64 for reduced-precision schedules, complex128 for "fp64".
+    Returns (A, Bmf, flags)."""
+    import torch
+
+    sched = schedule(schedule_) if isinstance(schedule_, str) else schedule_
+    if H.dtype not in (torch.complex64, torch.complex128) or Y.dtype != H.dtype:
+        raise TypeError("H and Y must both be complex64 or both complex128")
+    if not (H.is_cuda and Y.is_cuda and sigma2.is_cuda) or sigma2.dtype != torch.float64:
+        raise TypeError("H, Y: CUDA tensors; sigma2: float64 CUDA tensor")
+    H, Y, sigma2 = H.contiguous(), Y.contiguous(), sigma2.contiguous()
+    B, Nbs, K = H.shape
+    if Y.dim() != 3 or Y.shape[:2] != (B, Nbs) or sigma2.shape != (B,):
+        raise ValueError("shape mismatch between H, Y and sigma2")
+    R = Y.shape[2]
+    odt = torch.complex128 if sched.work == FMT["fp64"] else torch.complex64
+    A = torch.empty((B, K, K), dtype=odt, device=H.device)
+    Bm = torch.empty((B, K, R), dtype=odt, device=H.device)
+    flags = torch.empty((B,), dtype=torch.int32, device=H.device)
+    ctx = ctx or _ctx_for(H.device.index or 0)
+    _check(lib().fpcg_gram(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
+                           ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                           1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
+                           ctypes.byref(sched), ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(Bm.data_ptr()),
+                           ctypes.c_void_p(flags.data_ptr())))
+    return A, Bm, flags
 
 
 def slice_qam(x, qam: int, stream=None):

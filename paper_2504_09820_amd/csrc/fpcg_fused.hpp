@@ -64,6 +64,11 @@ struct FusedParams {
     // block-Jacobi inverse of the iteration (diag(A)^{-1} without one),
     // [channel][user] (NULL: none)
     float* gain;
+    // optional: the Gram A (K x K) and matched filter B (K x R) of each
+    // channel in u_W, interleaved complex, written after step 1; the launch
+    // then ends there (no solve, no x_hat or labels; flags of step 1 only)
+    void* gram_out;
+    void* mf_out;
 };
 
 // Lanes of the symmetric block-Jacobi transform.  Pass 1 (rows) needs rows
@@ -129,7 +134,7 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     static constexpr int PPW = (NPAIR + NW - 1) / NW;
     static constexpr int MFPW = (F + NW - 1) / NW;
     static constexpr int LDA = KP + 1;
-    static constexpr int RC = 16;                     // antennas per refinement chunk
+    static constexpr int RC = NW >= 4 ? 8 : 16;       // antennas per refinement chunk
     static constexpr int NT = 64 * NW;
     // waves per SIMD the register allocation must allow without FP64
     // refinement (1 = no constraint): three for one-wave K <= 32 channels
@@ -151,10 +156,12 @@ template <int KP_, int NW_, int FMT_, int LB_> struct Cfg {
     __host__ __device__ static constexpr size_t sz_bj(bool split) {
         return (LB && !split) ? (LB > 8 ? 4 : 2) * W * KP * LB : 0;   // L = 16 also exchanges C here
     }
-    static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * 8 : 0;    // p exchange (doubles)
-    static constexpr size_t sz_red = (NW > 1) ? (size_t)2 * NW * 16 * 4 * 8 : 0;    // dot partials, 2 parities
-    static constexpr size_t sz_ref = (NW > 1) ? (size_t)NW * RC * 16 * 2 * 8 : 0;   // refinement partials
-    static constexpr size_t sz_ex = sz_xp + sz_red + sz_ref;
+    static constexpr size_t sz_xp = (NW > 1) ? (size_t)NW * 64 * 2 * SH * W : 0;    // p exchange (u_W)
+    static constexpr size_t sz_red = (NW > 1) ? (size_t)2 * NW * 16 * 4 * W : 0;    // dot partials, 2 parities
+    // refinement partials (doubles): used only between two solves, when the
+    // p exchange and the dot partials are idle, so they share that region
+    static constexpr size_t sz_ref = (NW > 1) ? (size_t)NW * RC * 16 * 2 * 8 : 0;
+    static constexpr size_t sz_ex = (sz_xp + sz_red) > sz_ref ? (sz_xp + sz_red) : sz_ref;
     __host__ __device__ static constexpr size_t sz_S(bool split) { return sz_bj(split) > sz_ex ? sz_bj(split) : sz_ex; }
     __host__ __device__ static constexpr size_t off_X(bool split) { return off_S + sz_S(split); }   // x slots [2][SH][NT]
     static constexpr size_t sz_X = 2 * W * SH * NT;
@@ -241,9 +248,9 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     double* sX64r = reinterpret_cast<double*>(spriv + off_X + (x_in_gram ? 0 : C::sz_X));   // refinement only
     double* sX64i = sX64r + SH * NT;
     unsigned char* scr = spriv + C::off_S - shift;
-    double* sXP = reinterpret_cast<double*>(scr);                       // [NW][64][2*SH]
-    double* sRed = reinterpret_cast<double*>(scr + C::sz_xp);          // [2][NW][16][4]
-    double* sRef = reinterpret_cast<double*>(scr + C::sz_xp + C::sz_red);   // [NW][RC][16][2]
+    Wt* sXP = reinterpret_cast<Wt*>(scr);                               // [NW][64][2*SH]
+    Wt* sRed = reinterpret_cast<Wt*>(scr + C::sz_xp);                  // [2][NW][16][4]
+    double* sRef = reinterpret_cast<double*>(scr);                      // [NW][RC][16][2], between solves
     __shared__ uint32_t sFlag;
     __shared__ float sMaxW[NW];
     __shared__ float sMaxC[NW][16];
@@ -518,6 +525,12 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                             Wt ar, ai;
                             gram_at(s, jj, row, cc, ar, ai);
                             const bool real_entry = row < K && cc < K;
+                            if (P.gram_out && real_entry && cblk == 0) {
+                                Wt* go = static_cast<Wt*>(P.gram_out) + (size_t)ch * K * K * 2;
+                                go[2 * (row * K + cc)] = ar;
+                                go[2 * (row * K + cc) + 1] = ai;
+                                if (f1 != f2) { go[2 * (cc * K + row)] = ar; go[2 * (cc * K + row) + 1] = -ai; }
+                            }
                             const float vr = real_entry ? (float)ar * sAs : 0.f;
                             const float vi = real_entry ? (float)ai * sAs : 0.f;
                             put(sA8r, row * KP + cc, vr);
@@ -558,6 +571,12 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                             ar = (row < K) ? ar + s2w : (Wt)1;
                         }
                         nfa = fma(ar, (Wt)0, fma(ai, (Wt)0, nfa));
+                        if (P.gram_out && row < K && cc < K && cblk == 0) {
+                            Wt* go = static_cast<Wt*>(P.gram_out) + (size_t)ch * K * K * 2;
+                            go[2 * (row * K + cc)] = ar;
+                            go[2 * (row * K + cc) + 1] = ai;
+                            if (f1 != f2) { go[2 * (cc * K + row)] = ar; go[2 * (cc * K + row) + 1] = -ai; }
+                        }
                         sAr[row * LDA + cc] = ar;
                         sAi[row * LDA + cc] = ai;
                         if (f1 != f2) {
@@ -580,6 +599,11 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                     Wt br = (Wt)gBr[s][jj], bi = (Wt)gBi[s][jj];
                     if constexpr (FMT == F8) { br = br * invH * invY; bi = bi * invH * invY; }
                     nfa = fma(br, (Wt)0, fma(bi, (Wt)0, nfa));
+                    if (P.mf_out && row < K && colv) {
+                        Wt* mo = static_cast<Wt*>(P.mf_out) + ((size_t)ch * K * R + (size_t)row * R + col) * 2;
+                        mo[0] = br;
+                        mo[1] = bi;
+                    }
                     bcr[s][jj] = br;
                     bci[s][jj] = bi;
                     if (!compact) {
@@ -601,6 +625,17 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     } else {
         if constexpr (MODE == MODE_SOLVE) myflag = *sgflag;
         bsync();
+        if constexpr (MODE == MODE_FULL) {
+            if (P.gram_out) {                          // step 1 only: its flags, then done
+                if (myflag) atomicOr(&sFlag, myflag);
+                __syncthreads();
+                if (tid == 0 && P.flags) {
+                    if (P.R <= 16) P.flags[ch] = sFlag;
+                    else if (sFlag) atomicOr(&P.flags[ch], sFlag);
+                }
+                return;
+            }
+        }
     }
 
 
@@ -985,19 +1020,19 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         for (int k = 0; k < 4; ++k)
             if (k < cnt) v[k] = col_sum(v[k]);
         if constexpr (NW > 1) {
-            double* red = sRed + parity * NW * 16 * 4;
+            Wt* red = sRed + parity * NW * 16 * 4;
             if (g == 0) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (k < cnt) red[(wave * 16 + n) * 4 + k] = (double)v[k];
+                    if (k < cnt) red[(wave * 16 + n) * 4 + k] = v[k];
             }
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k < cnt) {
-                    Wt s = (Wt)red[(0 * 16 + n) * 4 + k];
+                    Wt s = red[(0 * 16 + n) * 4 + k];
 #pragma unroll
-                    for (int w = 1; w < NW; ++w) s = s + (Wt)red[(w * 16 + n) * 4 + k];
+                    for (int w = 1; w < NW; ++w) s = s + red[(w * 16 + n) * 4 + k];
                     v[k] = s;
                 }
             }
@@ -1007,13 +1042,13 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
     // publish this wave's slots of p (NW > 1) so that other waves can read them
     auto publish = [&](const Wt* vr, const Wt* vi) {
         if constexpr (NW > 1) {
-            double* dst = sXP + ((size_t)wave * 64 + lane) * 2 * SH;
+            Wt* dst = sXP + ((size_t)wave * 64 + lane) * 2 * SH;
 #pragma unroll
-            for (int e = 0; e < SH; ++e) { dst[e] = (double)vr[e]; dst[SH + e] = (double)vi[e]; }
+            for (int e = 0; e < SH; ++e) { dst[e] = vr[e]; dst[SH + e] = vi[e]; }
         }
     };
     auto fetch = [&](int ws, int e, int part) -> Wt {
-        return (Wt)sXP[((size_t)ws * 64 + lane) * 2 * SH + part * SH + e];
+        return sXP[((size_t)ws * 64 + lane) * 2 * SH + part * SH + e];
     };
 
     const int base_c = (g * NW + wave) * SH;
@@ -1530,15 +1565,17 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
 // the other K <= 32 reduced-precision and FP32 builds, two for FP64 at
 // K <= 32 (a few registers spill, and it still measured 13 % faster than one
 // wave), no constraint for FP64 at K = 64, K = 128 and refinement builds.
-template <int KP, int FMT, int LB, bool SPLIT, bool REF, typename IOT> constexpr int fused_waves() {
+// Four-wave channels (K = 64) ask for two waves per SIMD: two channels per CU.
+template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT> constexpr int fused_waves() {
     if (REF) return 1;
+    if (NW >= 4) return 2;
     if (FMT == F64 && KP == 32) return 2;
     if (KP == 32 && (FMT == F16 || FMT == BF16) && LB == 4 && SPLIT && sizeof(IOT) == 4) return 4;
     return Cfg<KP, 1, FMT, LB>::MIN_WAVES;
 }
 
 template <int KP, int NW, int FMT, int LB, bool SPLIT, bool REF, typename IOT>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(fused_waves<KP, FMT, LB, SPLIT, REF, IOT>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(fused_waves<KP, NW, FMT, LB, SPLIT, REF, IOT>())))
 void fused_kernel(const FusedParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t ch = blockIdx.x;

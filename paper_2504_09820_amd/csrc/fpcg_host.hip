@@ -47,14 +47,30 @@ static std::vector<KernelEntry>& table() {
         register_f8(t);
         register_k128_f8(t);
         register_k128_f16(t);
+        register_k64w_f16(t);
+        register_k64w_f64(t);
     });
     return t;
 }
 
-static const KernelEntry* find_entry(int KP, int FMT, int LB, int io_c64) {
+// the entry for (KP, FMT, LB, io) with NW waves per channel; NW = 0 asks for
+// the default wave count of that K and format
+static const KernelEntry* find_entry(int KP, int FMT, int LB, int io_c64, int NW = 0) {
+    const int want = NW ? NW : waves_for(KP, FMT);
     for (const auto& e : table())
-        if (e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64) return &e;
+        if (e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64 && e.NW == want) return &e;
     return nullptr;
+}
+
+// wave counts built for (KP, FMT, LB, io), the default first
+static std::vector<int> built_waves(int KP, int FMT, int LB, int io_c64) {
+    std::vector<int> w;
+    if (find_entry(KP, FMT, LB, io_c64)) w.push_back(waves_for(KP, FMT));
+    for (const auto& e : table())
+        if (e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64 &&
+            std::find(w.begin(), w.end(), e.NW) == w.end())
+            w.push_back(e.NW);
+    return w;
 }
 
 // smallest padded K with a compiled variant for (K, fmt, L)
@@ -192,10 +208,16 @@ TuneKey tune_key(const Plan& plan, int32_t R, int32_t io_c64) {
 
 std::vector<int> launch_forms(const Plan& plan, int32_t R, int32_t io_c64) {
     (void)R;
-    std::vector<int> f{FPCG_LAUNCH_FUSED};
+    std::vector<int> f;
+    const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0, ref = plan.sched.refine_steps > 0 ? 1 : 0;
+    for (int nw : built_waves(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0)) {
+        const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0, nw);
+        if (!e || !e->fn[sp][ref]) continue;
+        if (e->lds(sp != 0, ref != 0, plan.sched.refresh_every) > 160 * 1024) continue;
+        f.push_back(FPCG_LAUNCH_FUSED | (nw << FPCG_LAUNCH_WAVES_SHIFT));
+    }
     const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
-    const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
-    if (e && e->pipe_fn[sp] && plan.sched.refine_steps == 0) f.push_back(FPCG_LAUNCH_PIPELINED);
+    if (e && e->pipe_fn[sp] && !ref) f.push_back(FPCG_LAUNCH_PIPELINED);
     return f;
 }
 
@@ -203,7 +225,18 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
                                int32_t Nbs, int32_t K, int32_t R, const void* H, const void* Y, int32_t io_c64,
                                const double* sigma2, int32_t qam, int32_t iters, void* xhat, uint8_t* labels,
                                uint32_t* flags, const LaunchExtra* ex) {
-    const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
+    // waves per channel requested with the form; the default where that
+    // count is not built for this shape class (or its layout would not fit)
+    const int nw = form >> FPCG_LAUNCH_WAVES_SHIFT;
+    form &= (1 << FPCG_LAUNCH_WAVES_SHIFT) - 1;
+    const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
+    const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
+    const KernelEntry* e = nullptr;
+    if (nw && form == FPCG_LAUNCH_FUSED) {
+        e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0, nw);
+        if (e && (!e->fn[sp][ref] || e->lds(sp != 0, ref != 0, plan.sched.refresh_every) > 160 * 1024)) e = nullptr;
+    }
+    if (!e) e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
     if (!e) return fail(FPCG_E_UNSUPPORTED, "variant missing");
     const bool indexed = ex && ex->chan_idx;
     const int64_t n = indexed ? ex->n : B;           // workgroups along x
@@ -236,8 +269,8 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
     p.chan_idx = indexed ? ex->chan_idx : nullptr;
     p.ab_hist = ex ? ex->ab_hist : nullptr;
     p.gain = ex ? ex->gain : nullptr;
-    const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
-    const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
+    p.gram_out = ex ? ex->gram_out : nullptr;
+    p.mf_out = ex ? ex->mf_out : nullptr;
     const int ncb = (R + 15) / 16;
     if (!ref && !ex && e->pipe_fn[sp] && form == FPCG_LAUNCH_PIPELINED) {
         // pipelined form: persistent two-wave workgroups, as many as fit at once
@@ -306,10 +339,15 @@ const char* fpcg_strerror(int32_t status) {
 
 const char* fpcg_last_error(void) { return g_last_error.c_str(); }
 
-fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out) {
+fpcg_status fpcg_create(int32_t device, size_t hbm_budget, const char* tune_table, fpcg_ctx** out) {
     clear_error();
     if (!out) return fail(FPCG_E_INVAL, "out is NULL");
     *out = nullptr;
+    if (tune_table) {                                 // validated before any device call
+        fpcg_ctx probe;
+        fpcg_status st = parse_tune_table(tune_table, &probe);
+        if (st != FPCG_OK) return st;
+    }
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(FPCG_E_DEVICE, "no HIP device");
     if (device < 0 || device >= count) return fail(FPCG_E_INVAL, "device %d not in [0, %d)", device, count);
@@ -328,6 +366,7 @@ fpcg_status fpcg_create(int32_t device, size_t hbm_budget, fpcg_ctx** out) {
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
     }
     (void)table();
+    if (tune_table) (void)parse_tune_table(tune_table, c);
     *out = c;
     return FPCG_OK;
 }
@@ -337,7 +376,10 @@ void fpcg_destroy(fpcg_ctx* ctx) { delete ctx; }
 fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
-    if (form < FPCG_LAUNCH_AUTO || form > FPCG_LAUNCH_PIPELINED) return fail(FPCG_E_INVAL, "launch form %d out of range", form);
+    const int base = form & ((1 << FPCG_LAUNCH_WAVES_SHIFT) - 1), nw = form >> FPCG_LAUNCH_WAVES_SHIFT;
+    if (form < 0 || base > FPCG_LAUNCH_PIPELINED || !(nw == 0 || nw == 1 || nw == 2 || nw == 4) ||
+        (nw && base != FPCG_LAUNCH_FUSED))
+        return fail(FPCG_E_INVAL, "launch form %d out of range", form);
     ctx->launch_form = form;
     return FPCG_OK;
 }
@@ -353,8 +395,11 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int
                         int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    fpcg_schedule rs;
+    fpcg_status st = resolve_schedule(ctx, B, Nbs, K, R, qam_order, iters, block_L, sched, &rs);
+    if (st != FPCG_OK) return st;
     Plan plan;
-    fpcg_status st = check_args(B, Nbs, K, R, qam_order, iters, block_L, sched, &plan);
+    st = check_args(B, Nbs, K, R, qam_order, iters, block_L, &rs, &plan);
     if (st != FPCG_OK) return st;
     if (B > 0 && (!H || !Y || !sigma2 || !xhat || !labels))
         return fail(FPCG_E_INVAL, "H, Y, sigma2, xhat and labels must be non-NULL");
@@ -369,8 +414,11 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, 
                            const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    fpcg_schedule rs;
+    fpcg_status st = resolve_schedule(ctx, B, Nbs, K, R, qam_order, iters, block_L, sched, &rs);
+    if (st != FPCG_OK) return st;
     Plan plan;
-    fpcg_status st = check_args(B, Nbs, K, R, qam_order, iters, block_L, sched, &plan);
+    st = check_args(B, Nbs, K, R, qam_order, iters, block_L, &rs, &plan);
     if (st != FPCG_OK) return st;
     if (chan_idx && (n_idx < 0 || n_idx > 0x7fffffffLL))
         return fail(FPCG_E_INVAL, "n_idx=%lld out of range [0, 2^31-1]", (long long)n_idx);
@@ -396,6 +444,30 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, 
     if (st == FPCG_OK && kappa) st = launch_kappa(s, ex.ab_hist, n, R, iters, chan_idx, B, kappa);
     if (ex.ab_hist) (void)hipFreeAsync(ex.ab_hist, s);
     return st;
+}
+
+fpcg_status fpcg_gram(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
+                      const void* Y, int32_t io_c64, const double* sigma2, const fpcg_schedule* sched, void* A_out,
+                      void* B_out, uint32_t* flags) {
+    clear_error();
+    if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    if (!sched) return fail(FPCG_E_INVAL, "sched is NULL");
+    fpcg_schedule s = *sched;
+    s.refresh_every = 0;
+    s.refine_steps = 0;
+    s.variant = 0;
+    Plan plan;
+    fpcg_status st = check_args(B, Nbs, K, R, 4, 0, 0, &s, &plan);
+    if (st != FPCG_OK) return st;
+    if (B > 0 && (!H || !Y || !sigma2 || !A_out || !B_out))
+        return fail(FPCG_E_INVAL, "H, Y, sigma2, A_out and B_out must be non-NULL");
+    if (B == 0) return FPCG_OK;
+    ScopedDevice sd(ctx->device);
+    LaunchExtra ex;
+    ex.gram_out = A_out;
+    ex.mf_out = B_out;
+    return launch_detect_form(ctx, (hipStream_t)stream, plan, FPCG_LAUNCH_FUSED, B, Nbs, K, R, H, Y, io_c64, sigma2, 4,
+                              0, nullptr, nullptr, flags, &ex);
 }
 
 fpcg_status fpcg_slice(void* stream, int64_t n, const void* x, int32_t x_c64, int32_t qam_order, uint8_t* labels) {

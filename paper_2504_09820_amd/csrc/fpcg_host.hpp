@@ -15,11 +15,16 @@
 // symmetric form, refresh on, complex64 I/O, several blocks of received vectors
 using fpcg_tune_key = std::tuple<int, int, int, int, int, int, int>;
 
+// (Nbs, K, block size) of a workload class whose expected condition number
+// the context holds for the precision heuristic
+using fpcg_kappa_key = std::tuple<int, int, int>;
+
 struct fpcg_ctx {
     int device = 0;
     size_t budget = 0;
     int launch_form = FPCG_LAUNCH_AUTO;
     std::map<fpcg_tune_key, int> tuned;   // launch form chosen by fpcg_autotune per shape class
+    std::map<fpcg_kappa_key, double> kappa;   // E{kappa} per workload class (fpcg_expected_kappa / fpcg_set_kappa)
 };
 
 namespace fpcg {
@@ -35,6 +40,13 @@ void clear_error();
 fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam, int32_t iters, int32_t L,
                        const fpcg_schedule* s, Plan* plan);
 
+// the schedule a NULL schedule stands for: the precision heuristic's format
+// for the context's E{kappa} of (Nbs, K, L) (fpcg_policy.hip)
+fpcg_status resolve_schedule(const fpcg_ctx* ctx, int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam,
+                             int32_t iters, int32_t L, const fpcg_schedule* s, fpcg_schedule* out);
+// parse / print the context's table of tuned launch forms and E{kappa}
+fpcg_status parse_tune_table(const char* text, fpcg_ctx* ctx);
+
 using TuneKey = fpcg_tune_key;
 TuneKey tune_key(const Plan& plan, int32_t R, int32_t io_c64);
 // launch forms built for a plan (FPCG_LAUNCH_FUSED first)
@@ -46,6 +58,8 @@ struct LaunchExtra {
     int64_t n = 0;
     float* ab_hist = nullptr;
     float* gain = nullptr;
+    void* gram_out = nullptr;    // step 1 only: the Gram and matched filter in u_W
+    void* mf_out = nullptr;
 };
 // one launch in the given form (FPCG_LAUNCH_FUSED or FPCG_LAUNCH_PIPELINED;
 // a launch with extras always runs fused)

@@ -10,7 +10,7 @@
 namespace fpcg {
 
 struct KernelEntry {
-    int KP, NW, FMT, LB, io_c64;
+    int KP, NW, FMT, LB, io_c64;                 // NW: waves per channel
     int arow = 0;               // A kept only in the operand format (no u_W Gram in LDS)
     size_t (*lds)(bool split, bool refine, int refresh_every);   // dynamic LDS bytes of a launch
     // builds of the kernel: [symmetric block-Jacobi form][FP64 refinement]
@@ -29,10 +29,14 @@ void register_f16(std::vector<KernelEntry>& v);
 void register_f8(std::vector<KernelEntry>& v);
 void register_k128_f8(std::vector<KernelEntry>& v);
 void register_k128_f16(std::vector<KernelEntry>& v);
+void register_k64w_f16(std::vector<KernelEntry>& v);
+void register_k64w_f64(std::vector<KernelEntry>& v);
 
-// waves per channel for a padded K and operand format: one wave holds the
-// whole iterate (K/4 complex entries per lane) except where the FP64 vectors
-// would not fit the register file, and at K = 128 (two waves, K/8 entries)
+// default waves per channel for a padded K and operand format: one wave holds
+// the whole iterate (K/4 complex entries per lane) except where the FP64
+// vectors would not fit the register file, and at K = 128 (two waves, K/8
+// entries).  Other wave counts are registered beside the default where built
+// (each wave owns K/(4 NW) entries per lane, so a Jacobi block must fit them).
 constexpr int waves_for(int KP, int FMT) { return ((FMT == F64 && KP >= 64) || KP >= 128) ? 2 : 1; }
 
 template <int KP, int NW, int FMT, int LB, bool SP, bool RF, typename IOT>
@@ -44,9 +48,9 @@ void set_build(KernelEntry& e) {
 }
 
 // LB = 0 builds only the plain form (the symmetric slot repeats it)
-template <int KP, int FMT, int LB, typename IOT>
+template <int KP, int FMT, int LB, typename IOT, int NW = waves_for(KP, FMT)>
 void add_entry(std::vector<KernelEntry>& v) {
-    constexpr int NW = waves_for(KP, FMT);
+    static_assert(LB == 0 || (KP / (4 * NW)) % LB == 0, "a Jacobi block lies in one lane's entries");
     using C = Cfg<KP, NW, FMT, LB>;
     KernelEntry e;
     e.KP = KP; e.NW = NW; e.FMT = FMT; e.LB = LB;
@@ -91,5 +95,10 @@ void add_entry(std::vector<KernelEntry>& v) {
 #define FPCG_ENTRIES_IO(KP_, FMT_, LB_) \
     FPCG_ENTRY(KP_, FMT_, LB_, float);  \
     FPCG_ENTRY(KP_, FMT_, LB_, double)
+
+// the same with NW_ waves per channel
+#define FPCG_ENTRIES_IO_NW(KP_, FMT_, LB_, NW_)    \
+    add_entry<KP_, FMT_, LB_, float, NW_>(v);    \
+    add_entry<KP_, FMT_, LB_, double, NW_>(v)
 
 }  // namespace fpcg

@@ -48,8 +48,11 @@ extern "C" fpcg_status fpcg_autotune(fpcg_ctx* ctx, void* stream, int64_t B, int
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
     if (reps < 1 || reps > 1000) return fail(FPCG_E_INVAL, "reps=%d must be in [1, 1000]", reps);
+    fpcg_schedule rs;
+    fpcg_status st = resolve_schedule(ctx, B, Nbs, K, R, qam_order, iters, block_L, sched, &rs);
+    if (st != FPCG_OK) return st;
     Plan plan;
-    fpcg_status st = check_args(B, Nbs, K, R, qam_order, iters, block_L, sched, &plan);
+    st = check_args(B, Nbs, K, R, qam_order, iters, block_L, &rs, &plan);
     if (st != FPCG_OK) return st;
     if (B < 1) return fail(FPCG_E_INVAL, "B=%lld: nothing to time", (long long)B);
     const std::vector<int> forms = launch_forms(plan, R, io_c64);

@@ -1,13 +1,15 @@
-"""Host-side precision selection (eq. heuristic and eq. heuristic_bj).
+"""Precision selection (eq. heuristic and eq. heuristic_bj).
 
 The heuristic asks for u_MV < 1 / (N^1.5 sqrt(kappa)) with kappa the expected
 condition number of the system the iteration runs on: A for FP-CG, the
-block-Jacobi preconditioned matrix for FP-BJ-CG (whose spectrum is that of
-T A T^H with T = blockdiag(C_i^{-1}), A_i = C_i C_i^H).  kappa is estimated
-once per workload class from a sample of its channels (the expectation that
-the heuristic's footnote allows), then the library's fpcg_select_precision
-picks the cheapest format below the bound.  This is calibration done on the
-host before any detection; nothing here runs per channel on the hot path.
+block-Jacobi preconditioned matrix for FP-BJ-CG.  kappa is estimated once per
+workload class on the device from a sample of its channels (the expectation
+that the heuristic's footnote allows; fpcg_expected_kappa), then the
+library's fpcg_select_precision picks the cheapest format below the bound.
+The context keeps the estimate, so a detection with no schedule
+(detect(..., schedule_=None)) runs in the heuristic's format.  Nothing here
+does the method's arithmetic: the helpers below only marshal the library's
+calls and apply the scalar bound.
 
 Per channel (the alternative the footnote also allows): a detection with a
 kappa output (fpcg_detect_ex) estimates each channel's kappa from its CG
@@ -21,27 +23,28 @@ from __future__ import annotations
 import numpy as np
 
 
-def expected_kappa(H, sigma2, L: int = 0, sample: int = 64, seed: int = 0) -> float:
-    """Mean 2-norm condition number over up to `sample` channels of A = H^H H +
-    sigma^2 I (L = 0) or of T A T^H with L x L Jacobi blocks (L > 0).
-    H is (B, Nbs, K) complex (numpy or a CPU-copyable tensor), sigma2 (B,)."""
-    H = np.asarray(H.cpu() if hasattr(H, "cpu") else H)
-    s2 = np.asarray(sigma2.cpu() if hasattr(sigma2, "cpu") else sigma2, dtype=np.float64)
-    B, _, K = H.shape
-    idx = np.random.default_rng(seed).choice(B, size=min(sample, B), replace=False)
-    kap = []
-    for c in idx:
-        h = H[c].astype(np.complex128)
-        a = h.conj().T @ h + s2[c] * np.eye(K)
-        if L > 0:
-            t = np.zeros_like(a)
-            for b in range(0, K, L):
-                ch = np.linalg.cholesky(a[b:b + L, b:b + L])
-                t[b:b + L, b:b + L] = np.linalg.solve(ch, np.eye(L))
-            a = t @ a @ t.conj().T
-        ev = np.linalg.eigvalsh(a)
-        kap.append(ev[-1] / ev[0])
-    return float(np.mean(kap))
+def expected_kappa(H, Y, sigma2, L: int = 0, sample: int = 64, ctx=None) -> float:
+    """E{kappa} of the iteration matrix of A = H^H H + sigma^2 I (L = 0) or of
+    its block-Jacobi preconditioned form (L > 0), estimated on the device from
+    up to `sample` channels spread over the batch (fpcg_expected_kappa) and
+    recorded in the context.  H (B, Nbs, K), Y (B, Nbs, R) complex and sigma2
+    (B,) float64: CUDA tensors, or numpy arrays copied to the device."""
+    import torch
+
+    from . import _ctx_for
+
+    dev = torch.device("cuda", ctx.device) if ctx is not None else torch.device("cuda:0")
+
+    def on_dev(a, dtype=None):
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a))
+        return a.to(dev, dtype=dtype) if dtype is not None else a.to(dev)
+
+    H = on_dev(H)
+    Y = on_dev(Y, H.dtype)
+    s2 = on_dev(sigma2, torch.float64)
+    ctx = ctx or _ctx_for(dev.index or 0)
+    return ctx.expected_kappa(H, Y, s2, L, sample)
 
 
 def choose_format(K: int, kappa: float, allow_fp8: bool = False) -> tuple[str, float]:

@@ -211,3 +211,34 @@ def test_server_submit_validates_shapes_before_the_library(fp):
         srv.submit(H, Y, s2, 16, 4)
     with pytest.raises(fp.FpcgError):
         srv.submit(None, Y, None, 16, 4, channels=7)
+
+
+def test_tune_table_is_validated_before_any_device_call(fp):
+    L = fp.lib()
+    h = ctypes.c_void_p()
+    for bad in (b"", b"[]", b"{", b'{"forms": [{"KP": 64}]}', b'{"kappa": [{"Nbs": 1, "K": 2, "L": 0, "kappa": 0.5}]}',
+                b'{"forms": [{"KP": 64, "fmt": 3, "L": 4, "split": 1, "refresh": 1, "c64": 1, "multi": 0, "form": 7}]}',
+                b'{"forms": []} x'):
+        assert L.fpcg_create(0, 0, bad, ctypes.byref(h)) == -1, bad
+        assert "tune table" in L.fpcg_last_error().decode()
+    good = (b'{"version": 1, "note": "x", "forms": [{"KP": 64, "fmt": 3, "L": 4, "split": 1, "refresh": 1, "c64": 1, '
+            b'"multi": 0, "form": 1025}], "kappa": [{"Nbs": 256, "K": 64, "L": 4, "kappa": 37.9}]}')
+    import torch
+
+    st = L.fpcg_create(0, 0, good, ctypes.byref(h))
+    if torch.cuda.is_available():
+        assert st == 0
+        L.fpcg_destroy(h)
+    else:
+        assert st == -3                    # parsed, then no device
+
+
+def test_policy_calls_validate_on_the_host(fp):
+    L = fp.lib()
+    n = ctypes.c_size_t()
+    assert L.fpcg_tune_table(None, None, 0, ctypes.byref(n)) == -1
+    assert L.fpcg_set_kappa(None, 256, 64, 4, 10.0) == -1
+    k = ctypes.c_double()
+    assert L.fpcg_expected_kappa(None, None, 8, 256, 64, 14, None, None, 1, None, 4, 16, ctypes.byref(k)) == -1
+    s = fp.schedule("fp8")
+    assert L.fpcg_gram(None, None, 8, 64, 32, 14, None, None, 1, None, ctypes.byref(s), None, None, None) == -1

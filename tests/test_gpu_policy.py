@@ -1,0 +1,134 @@
+"""The precision policy behind the C ABI: fpcg_gram against the oracle's
+emulated Gram, the device estimate of E{kappa} (fpcg_expected_kappa) against
+the oracle's spectrum, the NULL schedule (the heuristic's format for the
+context's E{kappa}) against the explicit schedule it stands for, and the
+tune table's round trip through fpcg_tune_table / fpcg_create."""
+import json
+
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import detect as D
+from oracle import theory as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(wl, io=np.complex64):
+    import torch
+
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(wl.H.astype(io)).to(dev), torch.from_numpy(wl.Y.astype(io)).to(dev),
+            torch.from_numpy(wl.sigma2).to(dev))
+
+
+@pytest.mark.parametrize("sched,K,Nbs,R,io", [("fp64", 32, 128, 14, np.complex128), ("fp32", 64, 256, 14, np.complex64),
+                                             ("bf16", 20, 50, 17, np.complex64), ("fp16", 128, 512, 5, np.complex64)])
+def test_gram_matches_oracle(sched, K, Nbs, R, io):
+    """a0-a1 alone: the Gram and matched filter as the detector forms them,
+    against the oracle's emulation of the same schedule (operands rounded,
+    products summed exactly and rounded once): within the FP32 rounding of
+    the accumulation order (Thm 1 with u = 2^-24), bitwise Hermitian."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    print(f"case gram {sched} K={K} Nbs={Nbs} R={R}", flush=True)
+    wl = W.draw(3, Nbs, K, R, 16, 15.0, 0.5, 0.5, seed=5 + K)
+    H, Y, s2 = _dev(wl, io)
+    A, Bm, fl = fp.gram(H, Y, s2, sched)
+    torch.cuda.synchronize()
+    A, Bm = A.cpu().numpy().astype(np.complex128), Bm.cpu().numpy().astype(np.complex128)
+    name = {"fp8": "e4m3"}.get(sched, sched)
+    Ao, Bo = D.gram(wl.H.astype(io).astype(np.complex128), wl.Y.astype(io).astype(np.complex128), wl.sigma2,
+                    D.schedule(name))
+    u = 2.0**-53 if sched == "fp64" else 2.0**-24
+    Hq = np.abs(wl.H.astype(np.complex128))
+    scale = np.conj(np.swapaxes(Hq, -1, -2)) @ Hq            # |H|^H |H|
+    tol = 2 * 2 * Nbs * u * scale + u * np.abs(Ao)
+    assert np.all(np.abs(A - Ao) <= tol + 1e-300)
+    Yq = np.abs(wl.Y.astype(np.complex128))
+    tolb = 2 * 2 * Nbs * u * (np.conj(np.swapaxes(Hq, -1, -2)) @ Yq) + u * np.abs(Bo)
+    assert np.all(np.abs(Bm - Bo) <= tolb + 1e-300)
+    assert np.array_equal(A, np.conj(np.swapaxes(A, -1, -2)))
+    assert not fl.cpu().numpy().any()
+
+
+@pytest.mark.parametrize("K,Nbs,L,zeta", [(32, 128, 0, 0.5), (32, 128, 8, 0.8), (64, 256, 4, 0.7)])
+def test_expected_kappa_against_spectrum(K, Nbs, L, zeta):
+    """E{kappa} from the device (FP64 CG coefficients, min(K, 32) steps):
+    at K <= 32 the Krylov space is full and the mean equals the exact
+    E{kappa} of the oracle's eigenvalues; at K = 64 it is a lower estimate
+    within 15 %."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    print(f"case expected kappa K={K} L={L} zeta={zeta}", flush=True)
+    wl = W.draw(256, Nbs, K, 4, 16, 20.0, zeta, zeta, seed=17 + K + L)
+    H, Y, s2 = _dev(wl)
+    ctx = fp.Context(0)
+    k_dev = ctx.expected_kappa(H, Y, s2, L, sample=64)
+    smp = (np.arange(64) * 256) // 64
+    k_ex = T.expected_kappa(wl.H[smp].astype(np.complex64).astype(np.complex128), wl.sigma2[smp], L)
+    print(f"  device {k_dev:.4f}  exact {k_ex:.4f}", flush=True)
+    if K <= 32:
+        assert abs(k_dev / k_ex - 1) < 1e-2
+    else:
+        assert 0.85 * k_ex <= k_dev <= k_ex * (1 + 1e-3)
+    tab = json.loads(ctx.tune_table())
+    assert {"Nbs": Nbs, "K": K, "L": L, "kappa": k_dev} in tab["kappa"]
+    ctx.close()
+
+
+def test_null_schedule_runs_the_heuristics_format():
+    """detect with no schedule: the heuristic's format for the context's
+    E{kappa}, the symmetric block-Jacobi form, FP32 work -- bitwise the
+    explicit schedule; without a kappa for the class it is refused."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    wl = W.draw(40, 128, 32, 14, 64, 20.0, 0.5, 0.5, seed=3)
+    H, Y, s2 = _dev(wl)
+    ctx = fp.Context(0)
+    with pytest.raises(fp.FpcgError):
+        fp.detect(H, Y, s2, 64, 12, 8, None, ctx=ctx)
+    for kappa, want in ((3.0, "fp16"), (500.0, "fp32"), (1e12, "fp64")):
+        ctx.set_kappa(128, 32, 8, kappa)
+        assert fp.select_precision(32, kappa, True)[0] == want
+        xa, la, fa = fp.detect(H, Y, s2, 64, 12, 8, None, ctx=ctx)
+        xb, lb, fb = fp.detect(H, Y, s2, 64, 12, 8, want, variant=2, ctx=ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(xa.cpu().numpy().view(np.uint8), xb.cpu().numpy().view(np.uint8)), kappa
+        assert np.array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    ctx.close()
+
+
+def test_tune_table_round_trip():
+    """Launch forms chosen by the autotuner and E{kappa} survive
+    fpcg_tune_table -> fpcg_create; the reloaded context launches in the
+    same form (bitwise the same result)."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    wl = W.draw(300, 256, 64, 14, 64, 15.0, 0.7, 0.7, seed=4)
+    H, Y, s2 = _dev(wl)
+    ctx = fp.Context(0)
+    form = ctx.autotune(300, 256, 64, 14, 64, 16, 4, "fp16", refresh_every=4, variant=2, reps=2)
+    ctx.set_kappa(256, 64, 4, 21.5)
+    text = ctx.tune_table()
+    tab = json.loads(text)
+    assert len(tab["forms"]) == 1 and tab["kappa"] == [{"Nbs": 256, "K": 64, "L": 4, "kappa": 21.5}]
+    ctx2 = fp.Context(0, tune_table=text)
+    assert json.loads(ctx2.tune_table()) == tab
+    ctx3 = fp.Context(0)
+    ctx3.set_launch_form(form)
+    xa, _, _ = fp.detect(H, Y, s2, 64, 16, 4, "fp16", refresh_every=4, variant=2, ctx=ctx2)
+    xb, _, _ = fp.detect(H, Y, s2, 64, 16, 4, "fp16", refresh_every=4, variant=2, ctx=ctx3)
+    torch.cuda.synchronize()
+    assert np.array_equal(xa.cpu().numpy().view(np.uint8), xb.cpu().numpy().view(np.uint8))
+    for c in (ctx, ctx2, ctx3):
+        c.close()
