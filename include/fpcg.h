@@ -267,8 +267,11 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
  * per-channel / per-column power-of-two scales for fp8, products accumulated
  * on the matrix cores, sigma^2 added to the rounded diagonal), written in u_W:
  * A_out (B, K, K) and B_out (B, K, R), interleaved complex64 for u_W = F32,
- * complex128 for F64, device memory.  A is Hermitian (the upper triangle is
- * formed, the lower one written as its conjugate).  flags (may be NULL)
+ * complex128 for F64, device memory.  The upper triangle of 16 x 16 tiles is
+ * formed and the tiles below it are written as conjugate transposes; inside
+ * the diagonal tiles both halves are the matrix cores' own sums, so A is
+ * Hermitian up to the FP32 (FP64) rounding of two accumulation orders.
+ * flags (may be NULL)
  * receives the flags of this step (NONFINITE, FP8_SAT).  refresh, refinement
  * and variant of `sched` are ignored.  Errors as fpcg_detect; sched must not
  * be NULL. */

@@ -72,6 +72,11 @@ def lib():
         return _lib
     if not os.path.exists(library_path):
         raise FpcgError(E_DEVICE, f"{library_path} is not built; run `python -m paper_2504_09820_amd.build`")
+    # torch first: the library's HIP runtime dependency then binds to the runtime
+    # torch has loaded (same soname), so the process holds one HIP runtime and
+    # torch's device memory and streams are that runtime's own
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(library_path)
     st = ctypes.c_int32
     vp = ctypes.c_void_p
@@ -296,7 +301,8 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     chan_idx (int32 CUDA tensor) restricts the launch to those channels;
     kappa (float32 CUDA tensor of B) receives per-channel condition-number
     estimates and gain (float32 CUDA tensor (B, K)) each user's effective
-    gain, the input of demap_maxlog (fpcg_detect_ex).
+    gain, the input of demap_maxlog (fpcg_detect_ex).  schedule_=None runs the precision heuristic's format for
+    the context's E{kappa} of the workload class.
     """
     import torch
 

@@ -408,10 +408,17 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int
                          xhat, labels, flags);
 }
 
-fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
-                           const void* Y, int32_t io_c64, const double* sigma2, int32_t qam_order, int32_t iters,
-                           int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags,
-                           const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain) {
+}  // extern "C"
+
+namespace fpcg {
+
+// fpcg_detect_ex: the coefficient record of the kappa output comes from the
+// stream-ordered pool
+static fpcg_status detect_ex_impl(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                                  const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                                  int32_t qam_order, int32_t iters, int32_t block_L, const fpcg_schedule* sched,
+                                  void* xhat, uint8_t* labels, uint32_t* flags, const int32_t* chan_idx,
+                                  int64_t n_idx, float* kappa, float* gain) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
     fpcg_schedule rs;
@@ -433,17 +440,31 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, 
     ex.n = n;
     ex.gain = gain;
     const size_t hist_bytes = kappa && iters > 0 ? (size_t)n * std::min(R, KAPPA_COLS) * iters * 2 * sizeof(float) : 0;
+    bool pooled = false;
     if (hist_bytes) {
         void* h = nullptr;
         if (hipMallocAsync(&h, hist_bytes, s) != hipSuccess || !h)
             return fail(FPCG_E_NOMEM, "coefficient record of %zu bytes", hist_bytes);
         ex.ab_hist = static_cast<float*>(h);
+        pooled = true;
     }
     st = launch_detect_form(ctx, s, plan, FPCG_LAUNCH_FUSED, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters,
                             xhat, labels, flags, &ex);
     if (st == FPCG_OK && kappa) st = launch_kappa(s, ex.ab_hist, n, R, iters, chan_idx, B, kappa);
-    if (ex.ab_hist) (void)hipFreeAsync(ex.ab_hist, s);
+    if (pooled) (void)hipFreeAsync(ex.ab_hist, s);
     return st;
+}
+
+}  // namespace fpcg
+
+extern "C" {
+
+fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
+                           const void* Y, int32_t io_c64, const double* sigma2, int32_t qam_order, int32_t iters,
+                           int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags,
+                           const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain) {
+    return detect_ex_impl(ctx, stream, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters, block_L, sched, xhat,
+                          labels, flags, chan_idx, n_idx, kappa, gain);
 }
 
 fpcg_status fpcg_gram(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,

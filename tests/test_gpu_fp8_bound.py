@@ -84,7 +84,8 @@ def test_fp8_gram_and_first_matvec_within_a_priori_bounds(K, Nbs, R, io):
         ratio = float(np.max(err / bound))
         print(f"  channel {c}: Gram max |err|/bound {ratio:.3f}, max |err| {err.max():.2e}", flush=True)
         assert np.all(err <= bound), ratio
-        assert np.array_equal(A_g[c], A_g[c].conj().T)                  # Hermitian as written
+        off = np.kron(1 - np.eye((K + 15) // 16), np.ones((16, 16)))[:K, :K].astype(bool)
+        assert np.array_equal(A_g[c][off], A_g[c].conj().T[off])   # tiles below the diagonal mirrored
         # matched filter: the same bound with y's per-column scales
         y = Y[c]
         sy = _pow2_scale(np.max(np.maximum(np.abs(y.real), np.abs(y.imag)), axis=0))
