@@ -261,6 +261,25 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream,
                            void* xhat, uint8_t* labels, uint32_t* flags,
                            const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain);
 
+/* fpcg_detect_ex without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The coefficient record of the kappa output lives in
+ * a static device array of FPCG_STATIC_SCRATCH_BYTES (16 MiB), one copy per
+ * GPU, bound when a context is created on that GPU and held until the process
+ * ends; n * min(R, 4) * iters * 8 bytes must fit it (n = n_idx, or B without
+ * chan_idx), else FPCG_E_INVAL.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller.  Arguments, results and other errors as
+ * fpcg_detect_ex (bitwise the same outputs). */
+#define FPCG_STATIC_SCRATCH_BYTES (16u << 20)
+fpcg_status fpcg_detect_ex_static(fpcg_ctx* ctx, void* stream,
+                                  int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                                  const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                                  int32_t qam_order, int32_t iters, int32_t block_L,
+                                  const fpcg_schedule* sched,
+                                  void* xhat, uint8_t* labels, uint32_t* flags,
+                                  const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain);
+
 /* Step a0-a1 on its own (Sec. II, eq. inversion): the Gram A = H^H H +
  * sigma^2 I and the matched filter B = H^H Y of every channel, formed exactly
  * as fpcg_detect forms them for `sched` (H and Y rounded to sched->gram_op,

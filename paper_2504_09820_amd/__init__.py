@@ -112,6 +112,8 @@ def lib():
     L.fpcg_detect_ex.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(Schedule),
                                  vp, vp, vp, vp, i64, vp, vp]
     L.fpcg_detect_ex.restype = st
+    L.fpcg_detect_ex_static.argtypes = L.fpcg_detect_ex.argtypes
+    L.fpcg_detect_ex_static.restype = st
     L.fpcg_gram.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, ctypes.POINTER(Schedule), vp, vp, vp]
     L.fpcg_gram.restype = st
     L.fpcg_demap_maxlog.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp]
@@ -292,7 +294,8 @@ def _check_tensor(t, name, shape, dtype, device):
 
 def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Schedule" = "fp64",
            refresh_every: int = 0, refine_steps: int = 0, variant: int = 0,
-           ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None, gain=None):
+           ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None, gain=None,
+           static_workspace: bool = False):
     """Run the detector on device tensors.
 
     H (B, Nbs, K) and Y (B, Nbs, R): complex64 or complex128 CUDA tensors,
@@ -301,7 +304,10 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     chan_idx (int32 CUDA tensor) restricts the launch to those channels;
     kappa (float32 CUDA tensor of B) receives per-channel condition-number
     estimates and gain (float32 CUDA tensor (B, K)) each user's effective
-    gain, the input of demap_maxlog (fpcg_detect_ex).  schedule_=None runs the precision heuristic's format for
+    gain, the input of demap_maxlog (fpcg_detect_ex).  static_workspace=True
+    runs such launches through fpcg_detect_ex_static, which allocates
+    nothing (its workspace is a fixed per-GPU array; calls that overlap on
+    one GPU race).  schedule_=None runs the precision heuristic's format for
     the context's E{kappa} of the workload class.
     """
     import torch
@@ -336,7 +342,7 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         _check_tensor(xhat, "xhat", (B, K, R), H.dtype, H.device)
         _check_tensor(labels, "labels", (B, K, R), torch.uint8, H.device)
         _check_tensor(flags, "flags", (B,), torch.int32, H.device)
-    if chan_idx is not None or kappa is not None or gain is not None:
+    if chan_idx is not None or kappa is not None or gain is not None or static_workspace:
         if chan_idx is not None:
             if chan_idx.dtype != torch.int32 or not chan_idx.is_cuda or chan_idx.device != H.device:
                 raise TypeError("chan_idx must be an int32 CUDA tensor on the device of H")
@@ -345,7 +351,8 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         if gain is not None:
             _check_tensor(gain, "gain", (B, K), torch.float32, H.device)
         idx = chan_idx.contiguous() if chan_idx is not None else None
-        _check(lib().fpcg_detect_ex(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
+        entry = lib().fpcg_detect_ex_static if static_workspace else lib().fpcg_detect_ex
+        _check(entry(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
                                     ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                                     1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
                                     qam, iters, L, ctypes.byref(sched) if sched is not None else None,

@@ -156,6 +156,34 @@ struct ScopedDevice {
     }
 };
 
+// ------------------------------------------------------------------ static workspace
+// The coefficient record of fpcg_detect_ex_static (callers that cannot
+// allocate): a fixed device array, one copy on every GPU the library runs
+// on, held until the process ends.  In host code `scratch` names a host-side
+// stand-in; the address of a device's copy comes from hipGetSymbolAddress,
+// taken once per device in fpcg_create with that device current.
+static __device__ __align__(256) float scratch[FPCG_STATIC_SCRATCH_BYTES / sizeof(float)];
+
+static std::mutex g_scratch_mu;
+static std::map<int, float*> g_scratch_ptr;      // device -> its copy of `scratch`
+
+static fpcg_status bind_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return FPCG_OK;
+    void* ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !ptr)
+        return fail(FPCG_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(err));
+    g_scratch_ptr[device] = static_cast<float*>(ptr);
+    return FPCG_OK;
+}
+
+static float* scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
 __global__ void zero_u32(uint32_t* p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -354,6 +382,10 @@ fpcg_status fpcg_create(int32_t device, size_t hbm_budget, const char* tune_tabl
     ScopedDevice sd(device);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(FPCG_E_DEVICE, "hipMemGetInfo failed");
+    {
+        fpcg_status st = bind_scratch(device);        // this device is current (ScopedDevice)
+        if (st != FPCG_OK) return st;
+    }
     fpcg_ctx* c = new fpcg_ctx();
     c->device = device;
     c->budget = hbm_budget ? hbm_budget : (size_t)(0.8 * (double)free_b);
@@ -412,13 +444,14 @@ fpcg_status fpcg_detect(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int
 
 namespace fpcg {
 
-// fpcg_detect_ex: the coefficient record of the kappa output comes from the
-// stream-ordered pool
+// fpcg_detect_ex and its variant without allocation: the coefficient record
+// of the kappa output comes from the stream-ordered pool, or (use_static) is
+// the static array of this GPU
 static fpcg_status detect_ex_impl(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R,
                                   const void* H, const void* Y, int32_t io_c64, const double* sigma2,
                                   int32_t qam_order, int32_t iters, int32_t block_L, const fpcg_schedule* sched,
                                   void* xhat, uint8_t* labels, uint32_t* flags, const int32_t* chan_idx,
-                                  int64_t n_idx, float* kappa, float* gain) {
+                                  int64_t n_idx, float* kappa, float* gain, bool use_static) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
     fpcg_schedule rs;
@@ -441,7 +474,15 @@ static fpcg_status detect_ex_impl(fpcg_ctx* ctx, void* stream, int64_t B, int32_
     ex.gain = gain;
     const size_t hist_bytes = kappa && iters > 0 ? (size_t)n * std::min(R, KAPPA_COLS) * iters * 2 * sizeof(float) : 0;
     bool pooled = false;
-    if (hist_bytes) {
+    if (hist_bytes && use_static) {
+        // every entry the kappa kernel reads is written by this launch first,
+        // so the array needs no clearing between calls
+        if (hist_bytes > (size_t)FPCG_STATIC_SCRATCH_BYTES)
+            return fail(FPCG_E_INVAL, "coefficient record of %zu bytes exceeds the static workspace of %zu bytes",
+                        hist_bytes, (size_t)FPCG_STATIC_SCRATCH_BYTES);
+        ex.ab_hist = scratch_of(ctx->device);
+        if (!ex.ab_hist) return fail(FPCG_E_DEVICE, "no static workspace bound for device %d", ctx->device);
+    } else if (hist_bytes) {
         void* h = nullptr;
         if (hipMallocAsync(&h, hist_bytes, s) != hipSuccess || !h)
             return fail(FPCG_E_NOMEM, "coefficient record of %zu bytes", hist_bytes);
@@ -464,7 +505,16 @@ fpcg_status fpcg_detect_ex(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, 
                            int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags,
                            const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain) {
     return detect_ex_impl(ctx, stream, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters, block_L, sched, xhat,
-                          labels, flags, chan_idx, n_idx, kappa, gain);
+                          labels, flags, chan_idx, n_idx, kappa, gain, false);
+}
+
+fpcg_status fpcg_detect_ex_static(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                                  const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                                  int32_t qam_order, int32_t iters, int32_t block_L, const fpcg_schedule* sched,
+                                  void* xhat, uint8_t* labels, uint32_t* flags, const int32_t* chan_idx,
+                                  int64_t n_idx, float* kappa, float* gain) {
+    return detect_ex_impl(ctx, stream, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters, block_L, sched, xhat,
+                          labels, flags, chan_idx, n_idx, kappa, gain, true);
 }
 
 fpcg_status fpcg_gram(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
