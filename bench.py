@@ -967,29 +967,53 @@ def batch_bench(args):
         snr += 1.0
     snr_op = crossing(list(conv.items())) or snr
     berconv = ber_at(F64, itmax, snr_op)
+    def smallest_iters(cd, target, lo=1):
+        """Smallest I in [lo, itmax] whose BER is within the target: doubling,
+        then bisection (the BER falls with I up to rounding noise).  Returns
+        (I, reached)."""
+        hi, last_fail = lo, lo - 1
+        while hi <= itmax and ber_at(cd, hi, snr_op) > target:
+            last_fail = hi
+            hi = hi * 2 if hi < itmax else itmax + 1
+            if hi > itmax and last_fail < itmax:
+                hi = itmax
+        if hi > itmax:
+            return itmax, False
+        while hi - last_fail > 1:
+            mid = (hi + last_fail) // 2
+            if ber_at(cd, mid, snr_op) <= target:
+                hi = mid
+            else:
+                last_fail = mid
+        return hi, True
+
     I64 = args.iters64 or fixed
     if not I64:
-        I64 = itmax
-        for it in range(2, itmax + 1):
-            if ber_at(F64, it, snr_op) <= berconv * 1.02:
-                I64 = it
-                break
+        I64, _ = smallest_iters(F64, berconv * 1.02, lo=2)
     ber64 = ber_at(F64, I64, snr_op)
     log(f"BER 1e-3 operating point: converged FP64 crosses 1e-3 at {snr_op:.2f} dB (BER {berconv:.2e}); "
         f"FP64 CG I64={I64} {ber64:.2e}")
 
     def search(cd):
         if args.iters or fixed:
+            cd["parity_reached"] = None
             return args.iters or fixed
-        for it in range(1, itmax + 1):
-            if ber_at(cd, it, snr_op) <= ber64 * 1.02:
-                return it
-        return itmax
+        it, reached = smallest_iters(cd, ber64 * 1.02)
+        cd["parity_reached"] = reached
+        return it
 
     heur_cd = None
     hf = heur[cands[0]["L"]]["format"]
     if args.schedule == "auto" and hf != "fp64" and all(cd["sched"] != hf for cd in cands):
-        heur_cd = dict(cands[0], sched=hf, refresh=0, refine=0)
+        # the heuristic's format at the configured block size, else without a
+        # preconditioner where that is the combination built
+        for L in (cands[0]["L"], 0):
+            trial = dict(cands[0], sched=hf, refresh=0, refine=0, L=L, variant=cands[0]["variant"] if L else 0)
+            if fp.check(B, Nbs, K, R, q, 8, L, fp.schedule(hf, variant=trial["variant"])) == 0:
+                heur_cd = trial
+                break
+        if heur_cd is None:
+            log(f"the heuristic's {hf} is not built for K={K}")
     for cd in cands + ([heur_cd] if heur_cd else []):
         cd["iters"] = search(cd)
         cd["form"] = tune(cd, cd["iters"])
@@ -1033,6 +1057,7 @@ def batch_bench(args):
         wall_h, per_h = graph_timed(launcher(heur_cd, heur_cd["iters"]), max(5, args.steps // 4), 2, IDLE_S)
         heur_line = {"schedule": heur_cd["sched"], "L": heur_cd["L"], "variant": heur_cd["variant"],
                      "iters": heur_cd["iters"], "form": heur_cd["form"], "ber": heur_cd["ber"],
+                     "parity_reached": heur_cd.get("parity_reached"),
                      "p50_ms": round(float(np.median(per_h)), 5),
                      "value": round(B * R / (wall_h / max(5, args.steps // 4)), 1),
                      "speedup_vs_fp64_cg": round((wall_64 / steps64) / (wall_h / max(5, args.steps // 4)), 3)}

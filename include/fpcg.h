@@ -158,11 +158,20 @@ void fpcg_destroy(fpcg_ctx* ctx);
  * which runs the workgroup of nw waves where that count is built for the
  * launch's shape class (each wave then holds K/(4 nw) entries of every
  * iterate per lane, so a Jacobi block must fit them), else the default count.
+ *   FPCG_LAUNCH_SLAB       (K = 64 and K = 128; no refinement; L = 0 or 4)
+ *                          K/16 waves per channel, each holding its slab of
+ *                          rows of every iterate and its column slab of A in
+ *                          registers (the operand copies of A p and of the
+ *                          FP64 refresh); for K = 128 with FP64 or FP32
+ *                          operands, whose u_W matrix does not fit LDS, the
+ *                          only form built.
  * Forms and wave counts run the same per-channel algorithm; the fused and
  * pipelined forms of one wave count are bitwise identical, and other wave
- * counts differ only in the order of the Gram's and the inner products'
- * partial sums.  FPCG_E_INVAL for a NULL context or an unknown form. */
-enum { FPCG_LAUNCH_AUTO = 0, FPCG_LAUNCH_FUSED = 1, FPCG_LAUNCH_PIPELINED = 2 };
+ * counts and the slab form differ in the order in which the products and
+ * inner products are summed (another valid rounding order).  A form not
+ * built for a launch's shape class falls back to the default.
+ * FPCG_E_INVAL for a NULL context or an unknown form. */
+enum { FPCG_LAUNCH_AUTO = 0, FPCG_LAUNCH_FUSED = 1, FPCG_LAUNCH_PIPELINED = 2, FPCG_LAUNCH_SLAB = 3 };
 #define FPCG_LAUNCH_WAVES_SHIFT 8
 fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form);
 
@@ -203,8 +212,9 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  *   block_L must divide K; each lane of the kernel owns whole Jacobi blocks,
  *   so L <= 8 below K = 65 and L = 16 runs the K <= 128 build.
  *   65 <= K <= 128 is built for fp8, fp16 and bf16 operands, left block-Jacobi
- *   forms (variant 0 or 1) and no FP64 refresh; with fp8 also with FP64
- *   refinement.  Other combinations return FPCG_E_UNSUPPORTED.
+ *   forms (variant 0 or 1) and no FP64 refresh (with fp8 also with FP64
+ *   refinement), and for FP64 and FP32 operands without a preconditioner (the
+ *   slab form).  Other combinations return FPCG_E_UNSUPPORTED.
  *   sched = NULL selects the schedule by the precision heuristic (eq.
  *   heuristic for block_L = 0, eq. heuristic_bj otherwise): with kappa the
  *   expected condition number the context holds for (Nbs, K, block_L)

@@ -164,7 +164,7 @@ LAUNCH_WAVES_SHIFT = 8
 
 
 def _form_code(form: str) -> int:
-    base = {"auto": 0, "fused": 1, "pipelined": 2}
+    base = {"auto": 0, "fused": 1, "pipelined": 2, "slab": 3}
     if form in base:
         return base[form]
     if form.startswith("fused-w") and form[7:] in ("1", "2", "4"):
@@ -174,7 +174,7 @@ def _form_code(form: str) -> int:
 
 def _form_name(code: int) -> str:
     nw = code >> LAUNCH_WAVES_SHIFT
-    base = {0: "auto", 1: "fused", 2: "pipelined"}[code & ((1 << LAUNCH_WAVES_SHIFT) - 1)]
+    base = {0: "auto", 1: "fused", 2: "pipelined", 3: "slab"}[code & ((1 << LAUNCH_WAVES_SHIFT) - 1)]
     return f"{base}-w{nw}" if nw else base
 
 
@@ -247,8 +247,9 @@ class Context:
     def set_launch_form(self, form: str = "auto"):
         """"auto" (the library's choice), "fused" (one workgroup per channel),
         "fused-w1" / "fused-w2" / "fused-w4" (the fused form with that many
-        waves per channel where built for a launch's shape) or "pipelined"
-        (two-wave pipelined form where built)."""
+        waves per channel where built for a launch's shape), "pipelined"
+        (two-wave pipelined form where built) or "slab" (A held in registers
+        across K/16 waves, K = 64 and 128)."""
         _check(lib().fpcg_set_launch_form(self._h, _form_code(form)))
 
     def close(self):

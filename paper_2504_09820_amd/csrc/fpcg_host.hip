@@ -49,17 +49,39 @@ static std::vector<KernelEntry>& table() {
         register_k128_f16(t);
         register_k64w_f16(t);
         register_k64w_f64(t);
+        register_slab64(t);
+        register_slab64_f64(t);
+        register_slab128(t);
     });
     return t;
 }
 
-// the entry for (KP, FMT, LB, io) with NW waves per channel; NW = 0 asks for
-// the default wave count of that K and format
+// the fused-kernel entry for (KP, FMT, LB, io) with NW waves per channel; NW = 0
+// asks for the default wave count of that K and format
 static const KernelEntry* find_entry(int KP, int FMT, int LB, int io_c64, int NW = 0) {
     const int want = NW ? NW : waves_for(KP, FMT);
     for (const auto& e : table())
-        if (e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64 && e.NW == want) return &e;
+        if (e.kind == 0 && e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64 && e.NW == want) return &e;
     return nullptr;
+}
+
+// the slab-kernel entry for (KP, FMT, LB, io), if built
+static const KernelEntry* find_slab(int KP, int FMT, int LB, int io_c64) {
+    for (const auto& e : table())
+        if (e.kind == 1 && e.KP == KP && e.FMT == FMT && e.LB == LB && e.io_c64 == io_c64) return &e;
+    return nullptr;
+}
+
+// whether a built entry takes this schedule: its build exists (refinement for
+// the fused kernel, the FP64 refresh for the slab kernel) and its LDS fits
+static bool entry_takes(const KernelEntry* e, int LB, const fpcg_schedule& s) {
+    if (!e) return false;
+    const int sp = (LB > 0 && s.variant == 2) ? 1 : 0;
+    const int b = e->kind == 1 ? (s.refresh_every > 0 ? 1 : 0) : (s.refine_steps > 0 ? 1 : 0);
+    if (e->kind == 1 && s.refine_steps > 0) return false;
+    if (e->kind == 0 && e->arow && s.refresh_every > 0) return false;   // no u_W Gram to refresh from
+    if (!e->fn[sp][b]) return false;
+    return e->lds(sp != 0, s.refine_steps > 0, s.refresh_every) <= 160 * 1024;
 }
 
 // wave counts built for (KP, FMT, LB, io), the default first
@@ -79,8 +101,9 @@ static int pick_kp(int K, int FMT, int L) {
     for (int kp : kps) {
         if (kp < K) continue;
         const int sh = kp / (4 * waves_for(kp, FMT));
-        if (L > sh) continue;
         if (FMT == F8 && kp < 32) continue;
+        if (find_slab(kp, FMT, L, 1)) return kp;
+        if (L > sh) continue;
         if (!find_entry(kp, FMT, L, 1)) continue;
         return kp;
     }
@@ -124,16 +147,22 @@ fpcg_status check_args(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
     const int kp = pick_kp(K, fmt, L);
     if (!kp) return fail(FPCG_E_UNSUPPORTED, "no variant for K=%d fmt=%d L=%d", K, fmt, L);
     {
-        const KernelEntry* e = find_entry(kp, fmt, L, 1);   // the layout does not depend on the I/O type
+        // the layout does not depend on the I/O type; a shape class runs the
+        // fused kernel where built for the schedule, else the slab kernel
+        const KernelEntry* e = find_entry(kp, fmt, L, 1);
+        const KernelEntry* es = find_slab(kp, fmt, L, 1);
         const int sp = (L > 0 && s->variant == 2) ? 1 : 0, ref = s->refine_steps > 0 ? 1 : 0;
-        if (e->arow && s->refresh_every > 0)
-            return fail(FPCG_E_UNSUPPORTED, "K=%d: the FP64 refresh needs the u_W Gram, kept only for K <= 64", K);
-        if (!e->fn[sp][ref])
-            return fail(FPCG_E_UNSUPPORTED, "K=%d: %s%s not built for this format", K,
-                        sp ? "the symmetric block-Jacobi form" : "this form", ref ? " with refinement" : "");
-        const size_t lds = e->lds(L > 0 && s->variant == 2, s->refine_steps > 0, s->refresh_every);
-        if (lds > 160 * 1024)
-            return fail(FPCG_E_UNSUPPORTED, "this schedule at K=%d needs %zu bytes of LDS (160 KiB per workgroup)", K, lds);
+        if (!entry_takes(e, L, *s) && !entry_takes(es, L, *s)) {
+            if (e && e->arow && s->refresh_every > 0)
+                return fail(FPCG_E_UNSUPPORTED, "K=%d: the FP64 refresh needs the u_W Gram, kept only for K <= 64", K);
+            if (e && e->fn[sp][ref]) {
+                const size_t lds = e->lds(sp != 0, ref != 0, s->refresh_every);
+                return fail(FPCG_E_UNSUPPORTED, "this schedule at K=%d needs %zu bytes of LDS (160 KiB per workgroup)", K, lds);
+            }
+            return fail(FPCG_E_UNSUPPORTED, "K=%d: %s%s%s not built for this format", K,
+                        sp ? "the symmetric block-Jacobi form" : "this form", ref ? " with refinement" : "",
+                        s->refresh_every > 0 ? " with the FP64 refresh" : "");
+        }
     }
     if (plan) {
         plan->KP = kp;
@@ -240,12 +269,13 @@ std::vector<int> launch_forms(const Plan& plan, int32_t R, int32_t io_c64) {
     const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0, ref = plan.sched.refine_steps > 0 ? 1 : 0;
     for (int nw : built_waves(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0)) {
         const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0, nw);
-        if (!e || !e->fn[sp][ref]) continue;
-        if (e->lds(sp != 0, ref != 0, plan.sched.refresh_every) > 160 * 1024) continue;
+        if (!entry_takes(e, plan.LB, plan.sched)) continue;
         f.push_back(FPCG_LAUNCH_FUSED | (nw << FPCG_LAUNCH_WAVES_SHIFT));
     }
     const KernelEntry* e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
-    if (e && e->pipe_fn[sp] && !ref) f.push_back(FPCG_LAUNCH_PIPELINED);
+    if (entry_takes(e, plan.LB, plan.sched) && e->pipe_fn[sp] && !ref) f.push_back(FPCG_LAUNCH_PIPELINED);
+    if (entry_takes(find_slab(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0), plan.LB, plan.sched))
+        f.push_back(FPCG_LAUNCH_SLAB);
     return f;
 }
 
@@ -260,12 +290,25 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
     const int sp = (plan.LB > 0 && plan.sched.variant == 2) ? 1 : 0;
     const int ref = plan.sched.refine_steps > 0 ? 1 : 0;
     const KernelEntry* e = nullptr;
+    const bool extras_fused_only = ex && (ex->gain || ex->gram_out);   // outputs only the fused kernel writes
     if (nw && form == FPCG_LAUNCH_FUSED) {
         e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0, nw);
-        if (e && (!e->fn[sp][ref] || e->lds(sp != 0, ref != 0, plan.sched.refresh_every) > 160 * 1024)) e = nullptr;
+        if (!entry_takes(e, plan.LB, plan.sched)) e = nullptr;
     }
-    if (!e) e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
-    if (!e) return fail(FPCG_E_UNSUPPORTED, "variant missing");
+    if (!e && form == FPCG_LAUNCH_SLAB && !extras_fused_only) {
+        e = find_slab(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
+        if (!entry_takes(e, plan.LB, plan.sched)) e = nullptr;
+    }
+    if (!e) {
+        e = find_entry(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
+        if (!entry_takes(e, plan.LB, plan.sched)) e = nullptr;
+    }
+    if (!e && !extras_fused_only) {                   // shapes built only as slab kernels
+        e = find_slab(plan.KP, plan.FMT, plan.LB, io_c64 ? 1 : 0);
+        if (!entry_takes(e, plan.LB, plan.sched)) e = nullptr;
+    }
+    if (!e) return fail(FPCG_E_UNSUPPORTED, "no kernel built for this launch (K=%d, format %d, L=%d%s)", K, plan.FMT,
+                        plan.LB, extras_fused_only ? ", gain or Gram output" : "");
     const bool indexed = ex && ex->chan_idx;
     const int64_t n = indexed ? ex->n : B;           // workgroups along x
     if (B == 0 || n == 0) return FPCG_OK;
@@ -300,6 +343,15 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
     p.gram_out = ex ? ex->gram_out : nullptr;
     p.mf_out = ex ? ex->mf_out : nullptr;
     const int ncb = (R + 15) / 16;
+    if (e->kind == 1) {
+        dim3 grid((unsigned)n, (unsigned)((R + 15) / 16));
+        const int rf = plan.sched.refresh_every > 0 ? 1 : 0;
+        const size_t lds = e->lds(sp != 0, false, plan.sched.refresh_every);
+        e->launch[sp][rf](p, grid, lds, stream);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return fail(FPCG_E_DEVICE, "slab kernel launch: %s", hipGetErrorString(err));
+        return FPCG_OK;
+    }
     if (!ref && !ex && e->pipe_fn[sp] && form == FPCG_LAUNCH_PIPELINED) {
         // pipelined form: persistent two-wave workgroups, as many as fit at once
         const size_t lds = e->pipe_lds(sp != 0, p.refresh_every);
@@ -409,7 +461,7 @@ fpcg_status fpcg_set_launch_form(fpcg_ctx* ctx, int32_t form) {
     clear_error();
     if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
     const int base = form & ((1 << FPCG_LAUNCH_WAVES_SHIFT) - 1), nw = form >> FPCG_LAUNCH_WAVES_SHIFT;
-    if (form < 0 || base > FPCG_LAUNCH_PIPELINED || !(nw == 0 || nw == 1 || nw == 2 || nw == 4) ||
+    if (form < 0 || base > FPCG_LAUNCH_SLAB || !(nw == 0 || nw == 1 || nw == 2 || nw == 4) ||
         (nw && base != FPCG_LAUNCH_FUSED))
         return fail(FPCG_E_INVAL, "launch form %d out of range", form);
     ctx->launch_form = form;

@@ -1,0 +1,13 @@
+// Slab-kernel instantiations for K = 128 (eight waves per channel) with FP64
+// and FP32 operands: the u_W matrix does not fit LDS beside the rest, so only
+// the register-resident layout holds it.
+#include "fpcg_registry.hpp"
+
+namespace fpcg {
+
+void register_slab128(std::vector<KernelEntry>& v) {
+    FPCG_SLAB_IO(128, F64, 0);
+    FPCG_SLAB_IO(128, F32, 0);
+}
+
+}  // namespace fpcg

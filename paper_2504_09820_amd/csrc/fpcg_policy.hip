@@ -168,7 +168,7 @@ fpcg_status parse_tune_table(const char* text, fpcg_ctx* ctx) {
                             return fail(FPCG_E_INVAL, "tune table: a \"forms\" entry needs an integer \"%s\"", names[i]);
                     const int form = (int)v[7];
                     const int base = form & ((1 << FPCG_LAUNCH_WAVES_SHIFT) - 1), nw = form >> FPCG_LAUNCH_WAVES_SHIFT;
-                    if (form < 0 || base < FPCG_LAUNCH_FUSED || base > FPCG_LAUNCH_PIPELINED ||
+                    if (form < 0 || base < FPCG_LAUNCH_FUSED || base > FPCG_LAUNCH_SLAB ||
                         !(nw == 0 || nw == 1 || nw == 2 || nw == 4))
                         return fail(FPCG_E_INVAL, "tune table: launch form %d out of range", form);
                     forms[fpcg_tune_key((int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6])] = form;

@@ -6,11 +6,13 @@
 #include <vector>
 
 #include "fpcg_fused.hpp"
+#include "fpcg_slab.hpp"
 
 namespace fpcg {
 
 struct KernelEntry {
     int KP, NW, FMT, LB, io_c64;                 // NW: waves per channel
+    int kind = 0;                                // 0: fused_kernel; 1: slab_kernel (fn[sp][1]: the refresh build)
     int arow = 0;               // A kept only in the operand format (no u_W Gram in LDS)
     size_t (*lds)(bool split, bool refine, int refresh_every);   // dynamic LDS bytes of a launch
     // builds of the kernel: [symmetric block-Jacobi form][FP64 refinement]
@@ -31,6 +33,9 @@ void register_k128_f8(std::vector<KernelEntry>& v);
 void register_k128_f16(std::vector<KernelEntry>& v);
 void register_k64w_f16(std::vector<KernelEntry>& v);
 void register_k64w_f64(std::vector<KernelEntry>& v);
+void register_slab64(std::vector<KernelEntry>& v);
+void register_slab64_f64(std::vector<KernelEntry>& v);
+void register_slab128(std::vector<KernelEntry>& v);
 
 // default waves per channel for a padded K and operand format: one wave holds
 // the whole iterate (K/4 complex entries per lane) except where the FP64
@@ -89,6 +94,44 @@ void add_entry(std::vector<KernelEntry>& v) {
     }
     v.push_back(e);
 }
+
+// the slab kernel of (KP, FMT, LB): builds [symmetric form][FP64 refresh]
+// (FP64 operands: no refresh build)
+template <int KP, int FMT, int LB, bool SP, bool RF, typename IOT>
+void set_slab(KernelEntry& e) {
+    e.fn[SP][RF] = reinterpret_cast<const void*>(&slab_kernel<KP, FMT, LB, SP, RF, IOT>);
+    e.launch[SP][RF] = [](const FusedParams& p, dim3 grid, size_t lds, hipStream_t s) {
+        hipLaunchKernelGGL((slab_kernel<KP, FMT, LB, SP, RF, IOT>), grid, dim3(64 * (KP / 16)), lds, s, p);
+    };
+}
+
+template <int KP, int FMT, int LB, typename IOT>
+void add_slab_entry(std::vector<KernelEntry>& v) {
+    using C = SlabCfg<KP, FMT, LB>;
+    KernelEntry e;
+    e.KP = KP; e.NW = C::NW; e.FMT = FMT; e.LB = LB;
+    e.io_c64 = sizeof(IOT) == 4 ? 1 : 0;
+    e.kind = 1;
+    e.arow = 0;
+    e.lds = [](bool sp, bool, int f) -> size_t { return C::lds(sizeof(IOT) * 2, LB > 0 && sp, f > 0); };
+    constexpr bool RFB = FMT != F64 && KP == 64;       // refresh builds: reduced formats at K = 64
+    set_slab<KP, FMT, LB, false, false, IOT>(e);
+    if constexpr (RFB) set_slab<KP, FMT, LB, false, true, IOT>(e);
+    else { e.fn[0][1] = nullptr; e.launch[0][1] = nullptr; }
+    if constexpr (LB > 0) {
+        set_slab<KP, FMT, LB, true, false, IOT>(e);
+        if constexpr (RFB) set_slab<KP, FMT, LB, true, true, IOT>(e);
+        else { e.fn[1][1] = nullptr; e.launch[1][1] = nullptr; }
+    } else {
+        e.fn[1][0] = e.fn[0][0]; e.fn[1][1] = e.fn[0][1];
+        e.launch[1][0] = e.launch[0][0]; e.launch[1][1] = e.launch[0][1];
+    }
+    v.push_back(e);
+}
+
+#define FPCG_SLAB_IO(KP_, FMT_, LB_)            \
+    add_slab_entry<KP_, FMT_, LB_, float>(v);    \
+    add_slab_entry<KP_, FMT_, LB_, double>(v)
 
 #define FPCG_ENTRY(KP_, FMT_, LB_, IOT_) add_entry<KP_, FMT_, LB_, IOT_>(v)
 

@@ -1,0 +1,802 @@
+// The register-resident ("slab") detector kernel for K = 64 and K = 128.
+//
+// One workgroup of NW = K/16 waves handles one channel and one block of up to
+// 16 received vectors.  Wave w owns slab w: rows 16w .. 16w+15 of every
+// iterate (x, r, p, b) and columns 16w .. 16w+15 of the iteration matrix A.
+// Lane (g, n) of a wave holds, in the output layout of the fp32-accumulating
+// 16x16 matrix-core tiles, rows 4g + i (i < 4) of its slab and received-vector
+// column n; for A, rows 16f + 4g + i of column 16w + n for every row slab f.
+//
+//   1. Gram and matched filter (Sec. II, eq. inversion) on the matrix cores:
+//      the upper-triangle 16x16 tiles of A = H^H H + sigma^2 I are spread over
+//      the waves; every tile goes through LDS once and each wave reads its
+//      column slab back (tiles below the diagonal as conjugate transposes).
+//   2. Block-Jacobi setup (eq. pre_BJ) for L = 4: Cholesky of every 4 x 4
+//      diagonal block, T = C^{-1}; the symmetric form (the system of Thm 4)
+//      rewrites A <- T A T^H and b <- T b in registers (rows lane-local, columns
+//      across four adjacent lanes); Alg. 3 as printed keeps M_d = T^H T.
+//   3. (P)CG (Alg. 2 / Alg. 3): A p on the matrix cores with A's operand copy
+//      in registers -- A p for rows of slab w contracts A's row slab w, which is
+//      the conjugate of the column slab the wave holds, so every operand
+//      fragment is the lane's own value -- and p of every slab read from LDS
+//      (each wave publishes its own slab once per iteration).  Inner products
+//      are lane-local sums reduced over the lane groups and then over the
+//      waves in a fixed order.  The FP64 refresh r = b - A x uses the FP64
+//      matrix cores on the u_W copy of A, also in registers.
+//   4. Slicer epilogue; outputs staged in LDS and stored as whole chunks.
+//
+// The FP64 matrix core's output tile puts row 4i + g (not 4g + i) in lane
+// group g, element i; the FP64 operand copies of A hold column rho(n) in lane
+// n (rho(4i + g) = 4g + i) instead of column n, so its products land in the
+// same layout as the others.
+#pragma once
+
+#include "fpcg_fused.hpp"
+
+namespace fpcg {
+
+// row of a 16-row tile that the FP64 matrix core's output position m holds
+// when the operand's lane n carries row rho(n): rho(4i + g) = 4g + i
+__device__ __forceinline__ int rho16(int m) { return 4 * (m & 3) + (m >> 2); }
+
+template <int KP_, int FMT_, int LB_> struct SlabCfg {
+    static constexpr int KP = KP_, FMT = FMT_, LB = LB_;
+    static_assert(KP == 64 || KP == 128, "slab kernel: K = 64 or 128");
+    static_assert(FMT == F64 || FMT == F32 || FMT == F16 || FMT == BF16, "slab kernel: no fp8");
+    static_assert(LB == 0 || LB == 4, "slab kernel: L = 0 or 4");
+    static constexpr int NW = KP / 16, F = KP / 16, NT = 64 * NW;
+    static constexpr bool LOWP = (FMT == F16 || FMT == BF16);
+    using Wt = typename std::conditional<FMT == F64, double, float>::type;
+    static constexpr size_t W = sizeof(Wt);
+    // A p: fp16/bf16 16x16x32 over two row slabs; fp32 / fp64 16x16x4 over (slab, element)
+    static constexpr int KPL = LOWP ? 8 : 1;
+    using O = Op<FMT, KPL>;
+    using frag = typename O::frag;
+    // Gram / matched filter operands per lane and instruction, instructions per loaded block
+    static constexpr int KPLG = LOWP ? 8 : 1;
+    static constexpr int NSUB = LOWP ? 1 : (F <= 4 ? 4 : 2);
+    static constexpr int NLD = KPLG * NSUB;
+    static constexpr int KBG = 4 * NLD;               // antennas per loaded block
+    using OG = Op<FMT, KPLG>;
+    static constexpr int NTILE = F * (F + 1) / 2;
+    static constexpr int PPW = (NTILE + NW - 1) / NW;
+    // LDS: [main: Gram tiles, then the p / x exchange, then the staged outputs]
+    //      [D: diagonal blocks] [T: T blocks, then M_d for the left form] [red]
+    static constexpr size_t sz_tiles = (size_t)NTILE * 2 * 256 * W;
+    static constexpr size_t PSZ = LOWP ? 2 : W;       // bytes of one exchanged p value
+    static constexpr size_t sz_pb = 2 * (size_t)F * 2 * 4 * 64 * PSZ;   // [parity][slab][plane][elem][lane]
+    static constexpr size_t sz_xb = (size_t)F * 2 * 4 * 64 * W;         // [slab][plane][elem][lane]
+    __host__ __device__ static constexpr size_t sz_stage(size_t es) {
+        return (((size_t)KP * 16 * es + 15) & ~(size_t)15) + (size_t)KP * 16;
+    }
+    __host__ __device__ static constexpr size_t sz_main(size_t es, bool refresh) {
+        size_t a = sz_tiles, b = sz_pb + (refresh ? sz_xb : 0), c = sz_stage(es);
+        return a > b ? (a > c ? a : c) : (b > c ? b : c);
+    }
+    static constexpr size_t sz_d = LB ? 2 * W * KP * LB : 0;
+    static constexpr size_t sz_t = LB ? 2 * W * KP * LB : 0;
+    static constexpr size_t sz_red = 2 * 2 * (size_t)NW * 16 * W;      // [parity][value][wave][column]
+    __host__ __device__ static constexpr size_t lds(size_t es, bool split, bool refresh) {
+        return sz_main(es, refresh) + sz_d + (split ? 1 : 2) * sz_t + sz_red;
+    }
+};
+
+// Register budget in waves per SIMD: three (170 registers) where the build
+// fits without spilling, two for FP64, K = 128, and the FP32 or left-form
+// builds with the FP64 refresh (which keep a second copy of A and M_d).
+template <int KP, int FMT, int LB, bool SPLIT, bool RFR> constexpr int slab_waves() {
+    if (FMT == F64 || KP == 128) return 2;
+    if (RFR && (FMT == F32 || (LB > 0 && !SPLIT))) return 2;
+    return 3;
+}
+
+// index of the upper tile (i, j), i <= j, in row-major order of the upper triangle
+__host__ __device__ constexpr int tile_index(int i, int j, int F) { return i * F - i * (i - 1) / 2 + (j - i); }
+
+template <int KP, int FMT, int LB, bool SPLIT, bool RFR, typename IOT>
+__global__ __launch_bounds__(64 * (KP / 16)) __attribute__((amdgpu_waves_per_eu(slab_waves<KP, FMT, LB, SPLIT, RFR>())))
+void slab_kernel(const FusedParams P) {
+    using C = SlabCfg<KP, FMT, LB>;
+    using O = typename C::O;
+    using OG = Op<FMT, (SlabCfg<KP, FMT, LB>::LOWP && sizeof(IOT) == 8) ? 4 : SlabCfg<KP, FMT, LB>::KPLG>;
+    using Wt = typename C::Wt;
+    using frag = typename O::frag;
+    using gfrag = typename OG::frag;
+    using acc_t = typename O::acc;
+    using gacc_t = typename OG::acc;
+    constexpr int NW = C::NW, F = C::F, NT = C::NT, PPW = C::PPW;
+    // complex128 inputs hold twice the registers per loaded value: half the
+    // antennas per loaded block (fp16 / bf16 Gram on the 16x16x16 shape)
+    constexpr int KPLG = (C::LOWP && sizeof(IOT) == 8) ? 4 : C::KPLG;
+    constexpr int NLD = KPLG * C::NSUB, KBG = 4 * NLD;
+    constexpr bool split = (LB > 0) && SPLIT;
+    constexpr bool left = (LB > 0) && !SPLIT;
+    constexpr uint32_t ES = CxB<IOT>::bytes;
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    int64_t ch = blockIdx.x;
+    if (P.chan_idx) {
+        ch = P.chan_idx[blockIdx.x];
+        if (ch < 0 || ch >= P.B) return;
+    }
+    const int cblk = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int col = cblk * 16 + n;
+    const bool colv = col < P.R;
+    const int K = P.K, Nbs = P.Nbs, R = P.R;
+    const bool refresh = RFR && P.refresh_every > 0;   // RFR: built with the FP64 refresh
+
+    unsigned char* smain = smem;
+    const size_t main_bytes = C::sz_main(ES, refresh);
+    Wt* sD = reinterpret_cast<Wt*>(smem + main_bytes);                 // [K][L] re, then im
+    Wt* sT = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d);       // T blocks [K][L] re, im
+    Wt* sM = sT + 2 * KP * (LB ? LB : 1);                                // left form: M_d blocks
+    Wt* sRed = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d + (split ? 1 : 2) * C::sz_t);
+    __shared__ uint32_t sFlag;
+    if (tid == 0) sFlag = 0u;
+    uint32_t myflag = 0u;
+
+    const int64_t hoff = ch * (int64_t)Nbs * K, yoff = ch * (int64_t)Nbs * R;
+    const Buf bH(static_cast<const char*>(P.H) + hoff * ES, (uint32_t)Nbs * K * ES);
+    const Buf bY(static_cast<const char*>(P.Y) + yoff * ES, (uint32_t)Nbs * R * ES);
+    const double s2 = P.sigma2[ch];
+
+    // ------------------------------------------------------------ 1. Gram + matched filter
+    Wt* sTile = reinterpret_cast<Wt*>(smain);                            // [tile][plane][16 x 16]
+    Wt br_[4], bi_[4];                                // b (own slab, rows 4g + i), then b_bar = T b
+    {
+        gacc_t gAr[PPW], gAi[PPW], gBr, gBi;
+#pragma unroll
+        for (int s = 0; s < PPW; ++s) { gAr[s] = gacc_t{0, 0, 0, 0}; gAi[s] = gacc_t{0, 0, 0, 0}; }
+        gBr = gacc_t{0, 0, 0, 0};
+        gBi = gacc_t{0, 0, 0, 0};
+        constexpr int NSUB = C::NSUB;
+        uint32_t hl[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) hl[f] = (16 * f + n < K) ? (uint32_t)(16 * f + n) * ES : OOB;
+        const uint32_t yl = colv ? (uint32_t)col * ES : OOB;
+        const uint32_t hrow = (uint32_t)K * ES, yrow = (uint32_t)R * ES;
+        auto gram_loop = [&](auto hcp) {
+            for (int a0 = 0; a0 < Nbs; a0 += KBG) {
+                Wt hr[F][NLD], hi[F][NLD], yr[NLD], yi[NLD];
+                const uint32_t ab = (uint32_t)(a0 + g * NLD);
+#pragma unroll
+                for (int j = 0; j < NLD; ++j) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f)
+                        CxB<IOT>::template load<decltype(hcp)::value>(bH, hl[f] + (ab + j) * hrow, hr[f][j], hi[f][j]);
+                    CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
+                }
+#pragma unroll
+                for (int u = 0; u < NSUB; ++u) {
+                    gfrag Xr[F], Xi[F], nXi[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        Xr[f] = OG::pack(&hr[f][u * KPLG], 1.f);
+                        Xi[f] = OG::pack(&hi[f][u * KPLG], 1.f);
+                        nXi[f] = OG::neg(Xi[f]);
+                    }
+                    int q = 0;
+#pragma unroll
+                    for (int f1 = 0; f1 < F; ++f1)
+#pragma unroll
+                        for (int f2 = f1; f2 < F; ++f2) {
+                            if (q % NW == wave) {
+                                const int s = q / NW;
+                                gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
+                                gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
+                                gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
+                                gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
+                            }
+                            ++q;
+                        }
+                    // matched filter tile of this wave's slab
+                    const gfrag Yr = OG::pack(&yr[u * KPLG], 1.f), Yi = OG::pack(&yi[u * KPLG], 1.f);
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        if (f == wave) {
+                            gBr = OG::mfma(Xr[f], Yr, gBr);
+                            gBr = OG::mfma(Xi[f], Yi, gBr);
+                            gBi = OG::mfma(Xr[f], Yi, gBi);
+                            gBi = OG::mfma(nXi[f], Yr, gBi);
+                        }
+                    }
+                }
+            }
+        };
+        if (hrow % 128u == 0) gram_loop(std::integral_constant<int, CP_STREAM>{});
+        else gram_loop(std::integral_constant<int, 0>{});
+
+        // tiles into LDS, row-major per plane (sigma^2 on the diagonal, padding diagonal 1)
+        const Wt s2w = (Wt)s2;
+        Wt nfa = 0;
+        int q = 0;
+#pragma unroll
+        for (int f1 = 0; f1 < F; ++f1)
+#pragma unroll
+            for (int f2 = f1; f2 < F; ++f2) {
+                if (q % NW == wave) {
+                    const int s = q / NW;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int r = OG::crow(g, jj);
+                        Wt ar = (Wt)gAr[s][jj], ai = (Wt)gAi[s][jj];
+                        if (f1 == f2 && r == n) {
+                            ai = 0;
+                            ar = (16 * f1 + r < K) ? ar + s2w : (Wt)1;
+                        }
+                        nfa = fma(ar, (Wt)0, fma(ai, (Wt)0, nfa));
+                        sTile[((size_t)q * 2 + 0) * 256 + r * 16 + n] = ar;
+                        sTile[((size_t)q * 2 + 1) * 256 + r * 16 + n] = ai;
+                    }
+                }
+                ++q;
+            }
+        // the matched filter tile of this wave's slab: the fp32-accumulating
+        // shapes hold row 4g + i in element i already; the FP64 shape holds row
+        // 4i + g, which lane (i, n) passes back in element g
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if constexpr (FMT == F64) {
+                double vr[4], vi[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    vr[e] = __shfl((double)gBr[e], i * 16 + n);
+                    vi[e] = __shfl((double)gBi[e], i * 16 + n);
+                }
+                br_[i] = g == 0 ? vr[0] : g == 1 ? vr[1] : g == 2 ? vr[2] : vr[3];
+                bi_[i] = g == 0 ? vi[0] : g == 1 ? vi[1] : g == 2 ? vi[2] : vi[3];
+            } else {
+                br_[i] = (Wt)gBr[i];
+                bi_[i] = (Wt)gBi[i];
+            }
+            nfa = fma(br_[i], (Wt)0, fma(bi_[i], (Wt)0, nfa));
+        }
+        if (!__builtin_isfinite(nfa)) myflag |= FLAG_NONFINITE;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ column slab of A, own slab of b
+    // Acol[f][i]: A[16f + 4g + i][16 wave + n]; AcP[f][i]: the same for column
+    // 16 wave + rho(n) (the FP64 operand layout, for FP64 A p and the refresh)
+    constexpr bool NEED_STD = (FMT != F64);
+    constexpr bool NEED_PERM = (FMT == F64);          // (reduced formats keep a permuted copy for the refresh)
+    Wt Acr[F][4], Aci[F][4];                          // standard (reduced formats) or permuted (FP64)
+    Wt Apr[RFR && !NEED_PERM ? F : 1][4], Api[RFR && !NEED_PERM ? F : 1][4];   // permuted copy for the FP64 refresh
+    auto a_at = [&](int row, int c, Wt& re, Wt& im) {   // A[row][c] from the tiles in LDS
+        const int fr = row >> 4, fc = c >> 4, rr = row & 15, cc = c & 15;
+        if (fr <= fc) {
+            const int q = tile_index(fr, fc, F);
+            re = sTile[((size_t)q * 2 + 0) * 256 + rr * 16 + cc];
+            im = sTile[((size_t)q * 2 + 1) * 256 + rr * 16 + cc];
+        } else {
+            const int q = tile_index(fc, fr, F);
+            re = sTile[((size_t)q * 2 + 0) * 256 + cc * 16 + rr];
+            im = -sTile[((size_t)q * 2 + 1) * 256 + cc * 16 + rr];
+        }
+    };
+    const int cstd = 16 * wave + n, cperm = 16 * wave + rho16(n);
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * f + 4 * g + i;
+            a_at(row, NEED_STD ? cstd : cperm, Acr[f][i], Aci[f][i]);
+            if constexpr (RFR && !NEED_PERM) a_at(row, cperm, Apr[f][i], Api[f][i]);
+        }
+    if constexpr (LB > 0) {
+        // diagonal blocks of this slab (standard columns: tile (wave, wave) in Acr / Aci
+        // for the reduced formats; FP64 holds permuted columns, so read them from LDS)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * wave + 4 * g + i, c = 16 * wave + n;
+            if (row / LB == c / LB) {
+                Wt re, im;
+                a_at(row, c, re, im);
+                sD[row * LB + c % LB] = re;
+                sD[KP * LB + row * LB + c % LB] = im;
+            }
+        }
+    }
+    __syncthreads();                                  // every wave has its slab; the tile region is free
+
+    // ------------------------------------------------------------ 2. block-Jacobi setup (L = 4)
+    Wt Mr[LB ? 4 : 1][LB ? 4 : 1], Mi[LB ? 4 : 1][LB ? 4 : 1];   // this lane's block of M_d (left form)
+    if constexpr (LB > 0) {
+        {
+            const bool act = tid < KP;
+            const int t = act ? tid : 0;
+            const int i = t % LB, cb = t - i;
+            Wt cr[LB][LB], ci[LB][LB];
+#pragma unroll
+            for (int r = 0; r < LB; ++r)
+#pragma unroll
+                for (int c = 0; c <= r; ++c) { cr[r][c] = sD[(cb + r) * LB + c]; ci[r][c] = sD[KP * LB + (cb + r) * LB + c]; }
+            Wt diag = 0;
+#pragma unroll
+            for (int r = 0; r < LB; ++r)
+                if (r == i) diag = cr[r][r];
+            bool blk_bad = false;
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                Wt d = cr[j][j];
+                if (!(d > 0) || !__builtin_isfinite(d)) { blk_bad = true; d = 1; }
+                const Wt l = sqrt(d), inv = (Wt)1 / l;
+                cr[j][j] = l;
+                ci[j][j] = inv;
+#pragma unroll
+                for (int r = j + 1; r < LB; ++r) { cr[r][j] = cr[r][j] * inv; ci[r][j] = ci[r][j] * inv; }
+#pragma unroll
+                for (int r = j + 1; r < LB; ++r)
+#pragma unroll
+                    for (int c = j + 1; c <= r; ++c) {
+                        cr[r][c] = fma(-cr[r][j], cr[c][j], fma(-ci[r][j], ci[c][j], cr[r][c]));
+                        ci[r][c] = fma(-ci[r][j], cr[c][j], fma(cr[r][j], ci[c][j], ci[r][c]));
+                    }
+            }
+            Wt tr[LB], ti[LB];
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                const Wt inv_rr = ci[r][r];
+                Wt sr = 0, si = 0;
+#pragma unroll
+                for (int m = 0; m < r; ++m) {
+                    sr = fma(cr[r][m], tr[m], fma(-ci[r][m], ti[m], sr));
+                    si = fma(cr[r][m], ti[m], fma(ci[r][m], tr[m], si));
+                }
+                tr[r] = (r == i) ? inv_rr : (r > i ? -sr * inv_rr : (Wt)0);
+                ti[r] = (r > i) ? -si * inv_rr : (Wt)0;
+            }
+            if (blk_bad) {
+#pragma unroll
+                for (int r = 0; r < LB; ++r) {
+                    tr[r] = 0; ti[r] = 0;
+                    if (r == i) tr[r] = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / sqrt(diag) : (Wt)1;
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int r = 0; r < LB; ++r) {                   // column i of T
+                    sT[(cb + r) * LB + i] = tr[r];
+                    sT[KP * LB + (cb + r) * LB + i] = ti[r];
+                }
+                if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
+            }
+            if constexpr (left) {
+                __syncthreads();
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < LB; ++j) {                // M = T^H T: row i
+                        Wt mr = 0, mi = 0;
+#pragma unroll
+                        for (int m = 0; m < LB; ++m) {
+                            const Wt b_r = sT[(cb + m) * LB + j], b_i = sT[KP * LB + (cb + m) * LB + j];
+                            mr = fma(tr[m], b_r, fma(ti[m], b_i, mr));
+                            mi = fma(tr[m], b_i, fma(-ti[m], b_r, mi));
+                        }
+                        sM[(cb + i) * LB + j] = mr;
+                        sM[KP * LB + (cb + i) * LB + j] = mi;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // this lane's blocks: rows 16 wave + 4 g + (0..3) form block 4 wave + g
+        const int rb = 16 * wave + 4 * g;
+        if constexpr (left) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    Mr[r][j] = sM[(rb + r) * LB + j];
+                    Mi[r][j] = sM[KP * LB + (rb + r) * LB + j];
+                }
+        }
+        if constexpr (split) {
+            // A <- T A T^H.  Rows: tile f, lane group g are rows of block 4f + g,
+            // mixed lane-locally by that block of T.  Columns: column 16 wave + n
+            // is column n % 4 of block 4 wave + n / 4, whose other columns sit in
+            // the three neighbouring lanes of the quad.
+            auto rows_T = [&](Wt (&vr)[F][4], Wt (&vi)[F][4]) {
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int rbf = 16 * f + 4 * g;
+                    Wt t_r[4][4], t_i[4][4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int j = 0; j <= r; ++j) { t_r[r][j] = sT[(rbf + r) * LB + j]; t_i[r][j] = sT[KP * LB + (rbf + r) * LB + j]; }
+                    Wt ur[4], ui[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Wt sr = 0, si = 0;
+#pragma unroll
+                        for (int j = 0; j <= r; ++j) {
+                            sr = fma(t_r[r][j], vr[f][j], fma(-t_i[r][j], vi[f][j], sr));
+                            si = fma(t_r[r][j], vi[f][j], fma(t_i[r][j], vr[f][j], si));
+                        }
+                        ur[r] = sr; ui[r] = si;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) { vr[f][r] = ur[r]; vi[f][r] = ui[r]; }
+                }
+            };
+            // columns of the standard layout: lane n holds column n
+            auto cols_TH = [&](Wt (&vr)[F][4], Wt (&vi)[F][4], int cbase) {
+                // T block of column block cbase / 4 (T[cc][j], j <= cc) for this lane's column cc = n % 4
+                const int cc = n & 3;
+                Wt t_r[4], t_i[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    t_r[j] = sT[(cbase + cc) * LB + j];
+                    t_i[j] = sT[KP * LB + (cbase + cc) * LB + j];
+                }
+                const int q0 = lane & ~3;
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        Wt sr = 0, si = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {      // += W[.][j] conj(T[cc][j]), T[cc][j] = 0 for j > cc
+                            const Wt wr = __shfl(vr[f][i], q0 + j), wi = __shfl(vi[f][i], q0 + j);
+                            sr = fma(wr, t_r[j], fma(wi, t_i[j], sr));
+                            si = fma(wi, t_r[j], fma(-wr, t_i[j], si));
+                        }
+                        vr[f][i] = sr; vi[f][i] = si;
+                    }
+            };
+            if constexpr (FMT == F64) {
+                // permuted columns in registers: transform the standard ones, then permute
+                Wt sr_[F][4], si_[F][4];
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) a_at(16 * f + 4 * g + i, cstd, sr_[f][i], si_[f][i]);
+                rows_T(sr_, si_);
+                cols_TH(sr_, si_, 16 * wave + (n & ~3));
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        Acr[f][i] = __shfl(sr_[f][i], g * 16 + rho16(n));
+                        Aci[f][i] = __shfl(si_[f][i], g * 16 + rho16(n));
+                    }
+            } else {
+                rows_T(Acr, Aci);
+                cols_TH(Acr, Aci, 16 * wave + (n & ~3));
+                if constexpr (RFR) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            Apr[f][i] = __shfl(Acr[f][i], g * 16 + rho16(n));
+                            Api[f][i] = __shfl(Aci[f][i], g * 16 + rho16(n));
+                        }
+                }
+            }
+            // b_bar = T b (rows of block 4 wave + g)
+            Wt ur[4], ui[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Wt sr = 0, si = 0;
+#pragma unroll
+                for (int j = 0; j <= r; ++j) {
+                    const Wt t_r = sT[(rb + r) * LB + j], t_i = sT[KP * LB + (rb + r) * LB + j];
+                    sr = fma(t_r, br_[j], fma(-t_i, bi_[j], sr));
+                    si = fma(t_r, bi_[j], fma(t_i, br_[j], si));
+                }
+                ur[r] = sr; ui[r] = si;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { br_[r] = ur[r]; bi_[r] = ui[r]; }
+        }
+    }
+
+    // ------------------------------------------------------------ A operand in registers
+    // A p for rows of slab `wave` contracts row slab `wave` of A, the conjugate
+    // of the column slab held: A[16 wave + n'][16 f + 4 g' + k] = conj(Acol[f][k])
+    // of lane (g', n').  Re(W) = Ar pr + Ai pi, Im(W) = Ar pi - Ai pr (Ai = Im Acol).
+    constexpr int NCH = C::LOWP ? F / 2 : F * 4;      // contraction chunks
+    frag afr[NCH][2];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if constexpr (C::LOWP) {
+            Wt vr[8], vi[8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                vr[k] = Acr[2 * c][k]; vi[k] = Aci[2 * c][k];
+                vr[4 + k] = Acr[2 * c + 1][k]; vi[4 + k] = Aci[2 * c + 1][k];
+            }
+            afr[c][0] = O::pack(vr, 1.f);
+            afr[c][1] = O::pack(vi, 1.f);
+        } else {
+            afr[c][0] = (frag)Acr[c / 4][c % 4];
+            afr[c][1] = (frag)Aci[c / 4][c % 4];
+        }
+    }
+
+    // ------------------------------------------------------------ 3. (P)CG
+    unsigned char* sPB = smain;                                        // p exchange [2][F][2][4][64]
+    Wt* sXB = reinterpret_cast<Wt*>(smain + C::sz_pb);                // x exchange [F][2][4][64]
+    auto pb_at = [&](int par, int s, int pl, int e, int ln) -> size_t {
+        return ((((size_t)par * F + s) * 2 + pl) * 4 + e) * 64 + ln;
+    };
+    // publish this wave's slab of p in the operand format (reduced) or u_W
+    auto publish_p = [&](int par, const Wt* pr, const Wt* pi) {
+        if constexpr (C::LOWP) {
+            uint32_t* d = reinterpret_cast<uint32_t*>(sPB);
+            // four halves of a plane as two words: [par][slab][plane][lane] x 2 words
+            const size_t o = (((size_t)par * F + wave) * 2) * 64 * 2;
+            uint32_t w0, w1, v0, v1;
+            if constexpr (FMT == F16) {
+                w0 = f16x2_bits(pr[0], pr[1]); w1 = f16x2_bits(pr[2], pr[3]);
+                v0 = f16x2_bits(pi[0], pi[1]); v1 = f16x2_bits(pi[2], pi[3]);
+            } else {
+                w0 = bf16x2_bits(pr[0], pr[1]); w1 = bf16x2_bits(pr[2], pr[3]);
+                v0 = bf16x2_bits(pi[0], pi[1]); v1 = bf16x2_bits(pi[2], pi[3]);
+            }
+            *reinterpret_cast<u32x2*>(d + o + (size_t)lane * 2) = u32x2{w0, w1};
+            *reinterpret_cast<u32x2*>(d + o + 128 + (size_t)lane * 2) = u32x2{v0, v1};
+        } else {
+            Wt* d = reinterpret_cast<Wt*>(sPB);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                d[pb_at(par, wave, 0, e, lane)] = pr[e];
+                d[pb_at(par, wave, 1, e, lane)] = pi[e];
+            }
+        }
+    };
+    // B operand of chunk c, plane pl, from parity par
+    auto b_op = [&](int par, int c, int pl) -> frag {
+        if constexpr (C::LOWP) {
+            const uint32_t* d = reinterpret_cast<const uint32_t*>(sPB);
+            const size_t o0 = ((((size_t)par * F + 2 * c) * 2 + pl) * 64 + lane) * 2;
+            const size_t o1 = ((((size_t)par * F + 2 * c + 1) * 2 + pl) * 64 + lane) * 2;
+            const u32x2 a = *reinterpret_cast<const u32x2*>(d + o0);
+            const u32x2 b = *reinterpret_cast<const u32x2*>(d + o1);
+            return frag{a[0], a[1], b[0], b[1]};
+        } else {
+            const Wt* d = reinterpret_cast<const Wt*>(sPB);
+            return (frag)d[pb_at(par, c / 4, pl, c % 4, lane)];
+        }
+    };
+    auto neg_op = [&](frag v) -> frag {
+        if constexpr (C::LOWP) return O::neg(v);
+        else return -v;
+    };
+    // sums of a per-lane value over the column (lane groups, then waves in
+    // order), two values at once; slot k of parity par
+    auto reduce2 = [&](int par, Wt& v0, Wt& v1, int cnt) {
+        v0 = col_sum(v0);
+        if (cnt > 1) v1 = col_sum(v1);
+        Wt* red = sRed + (size_t)par * 2 * NW * 16;
+        if (g == 0) {
+            red[(0 * NW + wave) * 16 + n] = v0;
+            if (cnt > 1) red[(1 * NW + wave) * 16 + n] = v1;
+        }
+        __syncthreads();
+        Wt a = red[(0 * NW + 0) * 16 + n], b = cnt > 1 ? red[(1 * NW + 0) * 16 + n] : (Wt)0;
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            a = a + red[(0 * NW + w) * 16 + n];
+            if (cnt > 1) b = b + red[(1 * NW + w) * 16 + n];
+        }
+        v0 = a;
+        v1 = b;
+    };
+
+    Wt xr[4], xi[4], rr[4], ri[4], pr[4], pi[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { xr[e] = 0; xi[e] = 0; rr[e] = br_[e]; ri[e] = bi_[e]; }
+    auto apply_M = [&](const Wt* ur, const Wt* ui, Wt* zr, Wt* zi) {
+        if constexpr (left) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Wt sr = 0, si = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sr = fma(Mr[r][j], ur[j], fma(-Mi[r][j], ui[j], sr));
+                    si = fma(Mr[r][j], ui[j], fma(Mi[r][j], ur[j], si));
+                }
+                zr[r] = sr; zi[r] = si;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { zr[e] = ur[e]; zi[e] = ui[e]; }
+        }
+    };
+    apply_M(rr, ri, pr, pi);                          // p0 = M r0 (Alg. 3) or r0
+    int par = 0;
+    Wt rho_cur;
+    {
+        Wt v0 = 0, v1 = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { v0 = fma(rr[e], pr[e], v0); v0 = fma(ri[e], pi[e], v0); }
+        reduce2(par, v0, v1, 1);
+        rho_cur = v0;
+    }
+    publish_p(par, pr, pi);
+    __syncthreads();
+    // flags so far, wave-uniform
+    uint32_t wflag = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (__ballot((myflag >> b) & 1u) != 0) wflag |= 1u << b;
+    myflag = 0u;
+    bool live = true, broken = false;
+    for (int it = 1; it <= P.iters; ++it) {
+        // ---- varpi = A p   [u_MV]
+        acc_t Wr = acc_t{0, 0, 0, 0}, Wi = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const frag b_r = b_op(par, c, 0), b_i = b_op(par, c, 1);
+            Wr = O::mfma(afr[c][0], b_r, Wr);
+            Wr = O::mfma(afr[c][1], b_i, Wr);
+            Wi = O::mfma(afr[c][0], b_i, Wi);
+            Wi = O::mfma(afr[c][1], neg_op(b_r), Wi);
+        }
+        Wt wr[4], wi[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { wr[e] = (Wt)Wr[e]; wi[e] = (Wt)Wi[e]; }
+        // ---- phi = p^H varpi, rho_{i-1} (Alg. 3 as printed)  [u_IP]
+        const bool need_rp = left && (P.variant == 0);
+        Wt v0 = 0, v1 = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { v0 = fma(pr[e], wr[e], v0); v0 = fma(pi[e], wi[e], v0); }
+        if (need_rp) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { v1 = fma(rr[e], pr[e], v1); v1 = fma(ri[e], pi[e], v1); }
+        }
+        reduce2(par, v0, v1, need_rp ? 2 : 1);
+        const Wt ph = v0;
+        const Wt rho_prev = need_rp ? v1 : rho_cur;
+        // ---- guard, alpha, x and r  [u_W]
+        const bool ok = live && __builtin_isfinite(ph) && __builtin_isfinite(rho_prev) && ph > 0 && rho_prev > 0;
+        if (live && !ok && colv) broken = true;
+        live = ok;
+        Wt alpha_rec = 0, beta_rec = 0;
+        if (live) {
+            const Wt alpha = rho_prev / ph;
+            alpha_rec = alpha;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                xr[e] = fma(alpha, pr[e], xr[e]);
+                xi[e] = fma(alpha, pi[e], xi[e]);
+                rr[e] = fma(-alpha, wr[e], rr[e]);
+                ri[e] = fma(-alpha, wi[e], ri[e]);
+            }
+        }
+        // ---- FP64 residual refresh r = b - A x on the stored u_W matrix
+        if (RFR && refresh && it % P.refresh_every == 0 && it < P.iters) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sXB[(((size_t)wave * 2 + 0) * 4 + e) * 64 + lane] = xr[e];
+                sXB[(((size_t)wave * 2 + 1) * 4 + e) * 64 + lane] = xi[e];
+            }
+            __syncthreads();
+            f64x4 Rr = f64x4{0, 0, 0, 0}, Ri = f64x4{0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < F * 4; ++c) {
+                const int f = c / 4, k = c % 4;
+                double a_r, a_i;
+                if constexpr (NEED_PERM) { a_r = (double)Acr[f][k]; a_i = (double)Aci[f][k]; }
+                else { a_r = (double)Apr[RFR ? f : 0][k]; a_i = (double)Api[RFR ? f : 0][k]; }
+                const double x_r = (double)sXB[(((size_t)f * 2 + 0) * 4 + k) * 64 + lane];
+                const double x_i = (double)sXB[(((size_t)f * 2 + 1) * 4 + k) * 64 + lane];
+                Rr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, x_r, Rr, 0, 0, 0);
+                Rr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, x_i, Rr, 0, 0, 0);
+                Ri = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, x_i, Ri, 0, 0, 0);
+                Ri = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, -x_r, Ri, 0, 0, 0);
+            }
+            if (live) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    rr[e] = (Wt)((double)br_[e] - Rr[e]);
+                    ri[e] = (Wt)((double)bi_[e] - Ri[e]);
+                }
+            }
+            __syncthreads();                                // x exchange read by every wave
+        }
+        // ---- z = M r (left form) or r, rho_i, beta, p
+        Wt zr[4], zi[4];
+        apply_M(rr, ri, zr, zi);
+        v0 = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { v0 = fma(rr[e], zr[e], v0); v0 = fma(ri[e], zi[e], v0); }
+        reduce2(par ^ 1, v0, v1, 1);
+        const Wt rho_new = v0;
+        if (live) {
+            const Wt beta = rho_new / rho_prev;
+            beta_rec = beta;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pr[e] = fma(beta, pr[e], zr[e]);
+                pi[e] = fma(beta, pi[e], zi[e]);
+            }
+        }
+        rho_cur = rho_new;
+        if (P.ab_hist && g == 0 && wave == 0 && colv && col < KAPPA_COLS) {
+            const int nrec = R < KAPPA_COLS ? R : KAPPA_COLS;
+            float* h = P.ab_hist + (((int64_t)blockIdx.x * nrec + col) * P.iters + (it - 1)) * 2;
+            h[0] = (float)alpha_rec;
+            h[1] = (float)beta_rec;
+        }
+        par ^= 1;
+        publish_p(par, pr, pi);
+        __syncthreads();
+    }
+    if (broken) myflag |= FLAG_BREAKDOWN;
+
+    // ------------------------------------------------------------ 4. back-transform, slicer, stores
+    if constexpr (split) {                            // x = T^H x_bar (rows of block 4 wave + g)
+        const int rb = 16 * wave + 4 * g;
+        Wt ur[4], ui[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Wt sr = 0, si = 0;
+#pragma unroll
+            for (int j = r; j < 4; ++j) {             // += conj(T[j][r]) x_j
+                const Wt t_r = sT[(rb + j) * LB + r], t_i = sT[KP * LB + (rb + j) * LB + r];
+                sr = fma(t_r, xr[j], fma(t_i, xi[j], sr));
+                si = fma(t_r, xi[j], fma(-t_i, xr[j], si));
+            }
+            ur[r] = sr; ui[r] = si;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { xr[r] = ur[r]; xi[r] = ui[r]; }
+    }
+    {
+        const Wt nu = (Wt)P.nu, mm = (Wt)P.m;
+        const bool stage = R <= 16;
+        unsigned char* so_x = smain;
+        unsigned char* so_l = so_x + (((size_t)K * R * ES + 15) & ~(size_t)15);
+        if (stage) __syncthreads();                     // every wave is done with the exchange region
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 16 * wave + 4 * g + e;
+            const uint8_t lab = slice_label<Wt>(xr[e], xi[e], nu, mm, P.m, P.bits);
+            if (stage) {
+                if (colv && row < K) {
+                    const int o = row * R + col;
+                    IOT* px = reinterpret_cast<IOT*>(so_x + (size_t)o * ES);
+                    px[0] = (IOT)xr[e];
+                    px[1] = (IOT)xi[e];
+                    so_l[o] = lab;
+                }
+            } else {
+                const Buf bXo(static_cast<char*>(P.xhat) + (int64_t)ch * K * R * ES, (uint32_t)K * R * ES);
+                const Buf bLo(P.labels + (int64_t)ch * K * R, (uint32_t)K * R);
+                const uint32_t o = (uint32_t)row * R;
+                CxB<IOT>::store(bXo, (colv && row < K ? (uint32_t)col * ES : OOB) + o * ES, xr[e], xi[e]);
+                store_u8(bLo, (colv && row < K ? (uint32_t)col : OOB) + o, lab);
+            }
+        }
+        if (stage) {
+            __syncthreads();
+            const Buf bXo(static_cast<char*>(P.xhat) + (int64_t)ch * K * R * ES, (uint32_t)K * R * ES);
+            const Buf bLo(P.labels + (int64_t)ch * K * R, (uint32_t)K * R);
+            const uint32_t nx = (uint32_t)K * R * ES, nl = (uint32_t)K * R;
+            for (uint32_t i = tid * 16u; i + 16u <= nx; i += NT * 16u)
+                store_b128<CP_STREAM>(bXo, i, *reinterpret_cast<const u32x4v*>(so_x + i));
+            if ((nx & 15u) && tid == 0) {
+                const uint32_t i = nx & ~15u;
+                store_b64<CP_STREAM>(bXo, i, *reinterpret_cast<const u32x2v*>(so_x + i));
+            }
+            for (uint32_t i = tid * 16u; i + 16u <= nl; i += NT * 16u)
+                store_b128<0>(bLo, i, *reinterpret_cast<const u32x4v*>(so_l + i));
+            for (uint32_t i = (nl & ~15u) + tid; i < nl; i += NT) store_u8(bLo, i, so_l[i]);
+        }
+    }
+    myflag |= wflag;
+    if (myflag) atomicOr(&sFlag, myflag);
+    __syncthreads();
+    if (tid == 0 && P.flags) {
+        if (P.R <= 16) P.flags[ch] = sFlag;
+        else if (sFlag) atomicOr(&P.flags[ch], sFlag);
+    }
+}
+
+}  // namespace fpcg

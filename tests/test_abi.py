@@ -65,7 +65,7 @@ def test_check_accepts_built_configurations(fp):
     ((10, 64, 8, 1, 16, -1, 0), -1),
     ((10, 64, 8, 1, 16, 8, 3), -1),     # L does not divide K
     ((10, 64, 8, 1, 16, 8, -4), -1),
-    ((10, 256, 128, 1, 16, 8, 0), -4),  # K = 128 not built for fp32 operands
+    ((10, 256, 128, 1, 16, 8, 8), -4),  # K = 128 with fp32 operands: no preconditioner only
     ((10, 512, 192, 1, 16, 8, 0), -4),  # K > 128 not built
     ((10, 64, 32, 1, 16, 8, 16), -4),   # L = 16 not built for fp32 operands
     ((10, 64, 32, 1, 16, 8, 32), -4),   # L = 32 not built
@@ -89,6 +89,11 @@ def test_check_large_k(fp):
     assert fp.check(5, 512, 128, 14, 256, 16, 16, fp.schedule("fp8", refresh_every=4)) == -4   # refresh
     assert fp.check(5, 512, 128, 14, 256, 16, 16, fp.schedule("fp16", refine_steps=1)) == -4   # LDS
     assert fp.check(5, 512, 128, 14, 256, 16, 16, fp.schedule("fp64")) == -4
+    assert fp.check(2048, 512, 128, 14, 256, 48, 0, fp.schedule("fp64")) == 0      # slab form
+    assert fp.check(2048, 512, 128, 14, 256, 48, 0, fp.schedule("fp32")) == 0
+    assert fp.check(5, 512, 128, 14, 256, 16, 0, fp.schedule("fp32", refresh_every=4)) == -4
+    assert fp.check(5, 512, 128, 14, 256, 16, 0, fp.schedule("fp64", refine_steps=1)) == -4
+    assert fp.check(5, 256, 64, 14, 64, 16, 4, fp.schedule("fp16", refresh_every=4, variant=2)) == 0
     assert fp.check(5, 256, 32, 14, 64, 16, 16, fp.schedule("fp16")) == 0      # L = 16 runs the K <= 128 build
 
 

@@ -610,3 +610,79 @@ def test_fp64_four_waves_converged_to_1e12():
     ctx.close()
     ref = oracle_detect(wl, 64, 192, 0, "fp64")
     assert np.max(col_rel(x.cpu().numpy(), ref.xhat)) < 1e-12
+
+
+# --------------------------------------------------------------- the slab form (A held in registers)
+SLAB_CASES = [
+    # name, K, Nbs, R, q, iters, L, sched, io, refresh, variant
+    ("fp16-L4-split-refresh4", 64, 256, 14, 64, 16, 4, "fp16", np.complex64, 4, 2),
+    ("fp16-L4-left-refresh4", 64, 256, 14, 64, 16, 4, "fp16", np.complex64, 4, 0),
+    ("fp16-L4-textbook", 64, 256, 14, 64, 16, 4, "fp16", np.complex64, 0, 1),
+    ("fp16-L0", 64, 256, 14, 64, 16, 0, "fp16", np.complex64, 0, 0),
+    ("bf16-L4-split-c128", 64, 256, 14, 64, 14, 4, "bf16", np.complex128, 0, 2),
+    ("fp32-L4-split", 64, 256, 14, 64, 16, 4, "fp32", np.complex64, 0, 2),
+    ("fp32-L0-refresh3", 64, 256, 14, 64, 12, 0, "fp32", np.complex64, 3, 0),
+    ("fp64-L4-split", 64, 256, 14, 64, 24, 4, "fp64", np.complex128, 0, 2),
+    ("fp64-L0", 64, 256, 14, 64, 24, 0, "fp64", np.complex128, 0, 0),
+    ("K52-N200-R9-fp16-L4-split-refresh4", 52, 200, 9, 16, 14, 4, "fp16", np.complex64, 4, 2),
+    ("K64-R20-fp16-L4-split", 64, 256, 20, 64, 12, 4, "fp16", np.complex64, 0, 2),
+    ("K128-fp64-L0", 128, 512, 14, 256, 24, 0, "fp64", np.complex128, 0, 0),
+    ("K128-fp32-L0", 128, 512, 14, 256, 24, 0, "fp32", np.complex64, 0, 0),
+    ("K100-N300-R17-fp64-L0", 100, 300, 17, 64, 20, 0, "fp64", np.complex128, 0, 0),
+]
+
+
+def _slab_run(wl, q, iters, L, sched, io, refresh, variant):
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    ctx = fp.Context(0)
+    ctx.set_launch_form("slab")
+    dev = torch.device("cuda:0")
+    x, lab, fl = fp.detect(torch.from_numpy(wl.H.astype(io)).to(dev), torch.from_numpy(wl.Y.astype(io)).to(dev),
+                           torch.from_numpy(wl.sigma2).to(dev), q, iters, L, sched, refresh_every=refresh,
+                           variant=variant, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+    return x.cpu().numpy().astype(np.complex128), lab.cpu().numpy().astype(np.int64), fl.cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("case", SLAB_CASES, ids=[c[0] for c in SLAB_CASES])
+def test_slab_form_matches_oracle(case):
+    """The slab form (K/16 waves per channel, A's operand copies in registers,
+    p exchanged through LDS once per iteration) against the oracle, with
+    ragged K, Nbs and R and two blocks of received vectors."""
+    name, K, Nbs, R, q, iters, L, sched, io, refresh, variant = case
+    _say(f"case slab {name}")
+    zeta = 0.5 if K == 128 else 0.7
+    wl = _wl(5 if K < 128 else 3, Nbs, K, R, q, 15.0 if K < 128 else 25.0, zeta, 63)
+    x, lab, fl = _slab_run(wl, q, iters, L, sched, io, refresh, variant)
+    spread, ref = oracle_spread(wl, q, iters, L, sched, io, refresh=refresh, variant=variant)
+    _spread_parity(x, ref, spread, sched, name, io)
+    ok, n, bad = labels_consistent(lab, ref.labels, x, ref.xhat, q, x_alt=getattr(ref, "x_alt", None))
+    assert ok, (n, bad)
+    assert np.array_equal(fl, ref.flags.astype(np.int64))
+
+
+@pytest.mark.parametrize("K,Nbs,L", [(64, 256, 0), (64, 256, 4), (128, 512, 0)])
+def test_slab_fp64_converged_to_1e12(K, Nbs, L):
+    _say(f"case slab fp64 converged K={K} L={L}")
+    wl = _wl(4, Nbs, K, 14, 64, 20.0, 0.5, 64)
+    x, lab, fl = _slab_run(wl, 64, 3 * K, L, "fp64", np.complex128, 0, 2 if L else 0)
+    ref = oracle_detect(wl, 64, 3 * K, L, "fp64", variant=2 if L else 0)
+    assert np.max(col_rel(x, ref.xhat)) < 1e-12
+
+
+def test_slab_isolates_nonfinite_and_zero_channels():
+    _say("case slab isolation K=64 fp16 L=4 split")
+    wl = _wl(5, 256, 64, 5, 16, 15.0, 0.3, 65)
+    H = wl.H.copy()
+    Y = wl.Y.copy()
+    Y[1] = 0
+    H[3, 2, 5] = np.nan
+    sub = W.Workload(H=H, Y=Y, labels=wl.labels, X=wl.X, sigma2=wl.sigma2, q=16, snr_db=wl.snr_db)
+    x, lab, fl = _slab_run(sub, 16, 8, 4, "fp16", np.complex64, 0, 2)
+    ref = oracle_detect(wl, 16, 8, 4, "fp16", np.complex64, variant=2, H=H, Y=Y)
+    assert np.array_equal(fl, ref.flags.astype(np.int64)), (fl, ref.flags)
+    assert np.all(x[1] == 0) and np.all(x[3] == 0)
