@@ -1024,6 +1024,15 @@ def batch_bench(args):
             f"I={cd['iters']} BER {cd['ber']:.2e}, kernel p50 {cd['p50_ms']:.4f} ms ({cd['form']})")
     best = min(cands, key=lambda d: d["p50_ms"])
     form64 = tune(F64, I64)
+    # Remark 4's break-even rule on the measured (BER-parity) iteration counts
+    # of the configured block sizes of one format
+    rule = None
+    same = [cd for cd in cands if cd["sched"] == best["sched"] and cd["refresh"] == best["refresh"]]
+    if len(same) > 1:
+        L_rule, tot = precision.choose_block_size(K, iters={cd["L"]: cd["iters"] for cd in same})
+        rule = {"iters": {str(cd["L"]): cd["iters"] for cd in same}, "cost_in_iterations": {str(k): v for k, v in tot.items()},
+                "pick": L_rule}
+        log(f"Remark 4 break-even rule on the measured iterations: L={L_rule} ({tot})")
 
     # BER-vs-SNR gap at 1e-3 between the timed schedule and FP64 CG (and the converged solve)
     grid = [round(snr_op + d, 2) for d in (-2.0, -1.0, 0.0, 1.0, 2.0)]
@@ -1145,6 +1154,7 @@ def batch_bench(args):
                 "gap_db_vs_converged": None if gapc is None else round(gapc, 3)},
         "candidates": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in cd.items()} for cd in cands],
         "heuristic": {"picks": list(heur.values()), "timed_pick": heur_line},
+        "block_size_rule": rule,
         "error_vs_fp64_oracle": errs,
         "roofline": roofline,
         "cpu_baseline": cpu,

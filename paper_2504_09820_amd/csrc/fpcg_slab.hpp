@@ -69,8 +69,15 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
     __host__ __device__ static constexpr size_t sz_stage(size_t es) {
         return (((size_t)KP * 16 * es + 15) & ~(size_t)15) + (size_t)KP * 16;
     }
+    // The Gram's H: each wave loads its own slab and shares it through LDS
+    // (reduced formats and FP32, whose loads outweigh their products), or
+    // every wave loads every slab (FP64, bound by its matrix-core rate, where
+    // the exchange measured slower)
+    static constexpr bool STAGE = FMT != F64;
+    // H staged per loaded block: [2 buffers][slab][instruction][plane][lane] operand fragments
+    static constexpr size_t sz_hstage = STAGE ? 2 * (size_t)F * NSUB * 2 * 64 * sizeof(typename Op<FMT, KPLG>::frag) : 0;
     __host__ __device__ static constexpr size_t sz_main(size_t es, bool refresh) {
-        size_t a = sz_tiles, b = sz_pb + (refresh ? sz_xb : 0), c = sz_stage(es);
+        size_t a = sz_tiles > sz_hstage ? sz_tiles : sz_hstage, b = sz_pb + (refresh ? sz_xb : 0), c = sz_stage(es);
         return a > b ? (a > c ? a : c) : (b > c ? b : c);
     }
     static constexpr size_t sz_d = LB ? 2 * W * KP * LB : 0;
@@ -98,17 +105,14 @@ __global__ __launch_bounds__(64 * (KP / 16)) __attribute__((amdgpu_waves_per_eu(
 void slab_kernel(const FusedParams P) {
     using C = SlabCfg<KP, FMT, LB>;
     using O = typename C::O;
-    using OG = Op<FMT, (SlabCfg<KP, FMT, LB>::LOWP && sizeof(IOT) == 8) ? 4 : SlabCfg<KP, FMT, LB>::KPLG>;
+    using OG = typename C::OG;
     using Wt = typename C::Wt;
     using frag = typename O::frag;
     using gfrag = typename OG::frag;
     using acc_t = typename O::acc;
     using gacc_t = typename OG::acc;
     constexpr int NW = C::NW, F = C::F, NT = C::NT, PPW = C::PPW;
-    // complex128 inputs hold twice the registers per loaded value: half the
-    // antennas per loaded block (fp16 / bf16 Gram on the 16x16x16 shape)
-    constexpr int KPLG = (C::LOWP && sizeof(IOT) == 8) ? 4 : C::KPLG;
-    constexpr int NLD = KPLG * C::NSUB, KBG = 4 * NLD;
+    constexpr int KPLG = C::KPLG, NLD = C::NLD, KBG = C::KBG;
     constexpr bool split = (LB > 0) && SPLIT;
     constexpr bool left = (LB > 0) && !SPLIT;
     constexpr uint32_t ES = CxB<IOT>::bytes;
@@ -153,29 +157,100 @@ void slab_kernel(const FusedParams P) {
         gBr = gacc_t{0, 0, 0, 0};
         gBi = gacc_t{0, 0, 0, 0};
         constexpr int NSUB = C::NSUB;
-        uint32_t hl[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) hl[f] = (16 * f + n < K) ? (uint32_t)(16 * f + n) * ES : OOB;
+        // Each wave loads only its own slab of H (columns 16 wave + n), rounds
+        // it to the operand format and publishes the fragments in LDS; every
+        // wave then reads the slabs its tiles need from there.  The next
+        // block's loads are issued before this block's products, so one
+        // block's memory latency hides behind the other's arithmetic.
+        const uint32_t hl = (16 * wave + n < K) ? (uint32_t)(16 * wave + n) * ES : OOB;
         const uint32_t yl = colv ? (uint32_t)col * ES : OOB;
         const uint32_t hrow = (uint32_t)K * ES, yrow = (uint32_t)R * ES;
-        auto gram_loop = [&](auto hcp) {
+        // FP64: every wave loads every slab, no exchange
+        auto gram_all = [&](auto hcp) {
+            uint32_t hlf[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) hlf[f] = (16 * f + n < K) ? (uint32_t)(16 * f + n) * ES : OOB;
             for (int a0 = 0; a0 < Nbs; a0 += KBG) {
-                Wt hr[F][NLD], hi[F][NLD], yr[NLD], yi[NLD];
+                Wt xr_[F][NLD], xi_[F][NLD], yr_[NLD], yi_[NLD];
                 const uint32_t ab = (uint32_t)(a0 + g * NLD);
 #pragma unroll
                 for (int j = 0; j < NLD; ++j) {
 #pragma unroll
                     for (int f = 0; f < F; ++f)
-                        CxB<IOT>::template load<decltype(hcp)::value>(bH, hl[f] + (ab + j) * hrow, hr[f][j], hi[f][j]);
-                    CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
+                        CxB<IOT>::template load<decltype(hcp)::value>(bH, hlf[f] + (ab + j) * hrow, xr_[f][j], xi_[f][j]);
+                    CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr_[j], yi_[j]);
                 }
 #pragma unroll
                 for (int u = 0; u < NSUB; ++u) {
                     gfrag Xr[F], Xi[F], nXi[F];
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
-                        Xr[f] = OG::pack(&hr[f][u * KPLG], 1.f);
-                        Xi[f] = OG::pack(&hi[f][u * KPLG], 1.f);
+                        Xr[f] = OG::pack(&xr_[f][u * KPLG], 1.f);
+                        Xi[f] = OG::pack(&xi_[f][u * KPLG], 1.f);
+                        nXi[f] = OG::neg(Xi[f]);
+                    }
+                    int q = 0;
+#pragma unroll
+                    for (int f1 = 0; f1 < F; ++f1)
+#pragma unroll
+                        for (int f2 = f1; f2 < F; ++f2) {
+                            if (q % NW == wave) {
+                                const int s = q / NW;
+                                gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
+                                gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
+                                gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
+                                gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
+                            }
+                            ++q;
+                        }
+                    const gfrag Yr = OG::pack(&yr_[u * KPLG], 1.f), Yi = OG::pack(&yi_[u * KPLG], 1.f);
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        if (f == wave) {
+                            gBr = OG::mfma(Xr[f], Yr, gBr);
+                            gBr = OG::mfma(Xi[f], Yi, gBr);
+                            gBi = OG::mfma(Xr[f], Yi, gBi);
+                            gBi = OG::mfma(nXi[f], Yr, gBi);
+                        }
+                    }
+                }
+            }
+        };
+        gfrag* sStage = reinterpret_cast<gfrag*>(smain);                 // [2][F][NSUB][2][64]
+        auto st_at = [&](int buf, int f, int u, int pl) -> int { return (((buf * F + f) * NSUB + u) * 2 + pl) * 64 + lane; };
+        Wt hr[NLD], hi[NLD], yr[NLD], yi[NLD];        // the block in flight
+        auto gram_loop = [&](auto hcp) {
+            auto load_block = [&](int a0) {
+                const uint32_t ab = (uint32_t)(a0 + g * NLD);
+#pragma unroll
+                for (int j = 0; j < NLD; ++j) {
+                    CxB<IOT>::template load<decltype(hcp)::value>(bH, hl + (ab + j) * hrow, hr[j], hi[j]);
+                    CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
+                }
+            };
+            const int nblk = (Nbs + KBG - 1) / KBG;
+            load_block(0);
+            for (int b = 0; b < nblk; ++b) {
+                const int buf = b & 1;
+                gfrag Wr_[NSUB], Wi_[NSUB], Yr[NSUB], Yi[NSUB];
+#pragma unroll
+                for (int u = 0; u < NSUB; ++u) {
+                    Wr_[u] = OG::pack(&hr[u * KPLG], 1.f);
+                    Wi_[u] = OG::pack(&hi[u * KPLG], 1.f);
+                    Yr[u] = OG::pack(&yr[u * KPLG], 1.f);
+                    Yi[u] = OG::pack(&yi[u * KPLG], 1.f);
+                    sStage[st_at(buf, wave, u, 0)] = Wr_[u];
+                    sStage[st_at(buf, wave, u, 1)] = Wi_[u];
+                }
+                __syncthreads();                      // every slab of this block published
+                if (b + 1 < nblk) load_block((b + 1) * KBG);
+#pragma unroll
+                for (int u = 0; u < NSUB; ++u) {
+                    gfrag Xr[F], Xi[F], nXi[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        Xr[f] = sStage[st_at(buf, f, u, 0)];
+                        Xi[f] = sStage[st_at(buf, f, u, 1)];
                         nXi[f] = OG::neg(Xi[f]);
                     }
                     int q = 0;
@@ -193,21 +268,21 @@ void slab_kernel(const FusedParams P) {
                             ++q;
                         }
                     // matched filter tile of this wave's slab
-                    const gfrag Yr = OG::pack(&yr[u * KPLG], 1.f), Yi = OG::pack(&yi[u * KPLG], 1.f);
-#pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        if (f == wave) {
-                            gBr = OG::mfma(Xr[f], Yr, gBr);
-                            gBr = OG::mfma(Xi[f], Yi, gBr);
-                            gBi = OG::mfma(Xr[f], Yi, gBi);
-                            gBi = OG::mfma(nXi[f], Yr, gBi);
-                        }
-                    }
+                    gBr = OG::mfma(Wr_[u], Yr[u], gBr);
+                    gBr = OG::mfma(Wi_[u], Yi[u], gBr);
+                    gBi = OG::mfma(Wr_[u], Yi[u], gBi);
+                    gBi = OG::mfma(OG::neg(Wi_[u]), Yr[u], gBi);
                 }
             }
+            __syncthreads();                          // the stage is read before the tiles overwrite it
         };
-        if (hrow % 128u == 0) gram_loop(std::integral_constant<int, CP_STREAM>{});
-        else gram_loop(std::integral_constant<int, 0>{});
+        if constexpr (C::STAGE) {
+            if (hrow % 128u == 0) gram_loop(std::integral_constant<int, CP_STREAM>{});
+            else gram_loop(std::integral_constant<int, 0>{});
+        } else {
+            if (hrow % 128u == 0) gram_all(std::integral_constant<int, CP_STREAM>{});
+            else gram_all(std::integral_constant<int, 0>{});
+        }
 
         // tiles into LDS, row-major per plane (sigma^2 on the diagonal, padding diagonal 1)
         const Wt s2w = (Wt)s2;

@@ -125,15 +125,22 @@ def bj_setup_over_iteration(K: int, L: int) -> float:
     return (L * L) / K if L else 0.0
 
 
-def choose_block_size(K: int, kappas: dict, eps: float = 1e-3, setup_cost=bj_setup_over_iteration):
+def choose_block_size(K: int, kappas: dict | None = None, eps: float = 1e-3, setup_cost=bj_setup_over_iteration,
+                      iters: dict | None = None):
     """Block size by the break-even rule of Remark 4: with k(L) the iterations
-    the CG bound needs on the system preconditioned with L x L blocks (kappa
-    from `kappas`, {L: kappa}, L = 0 for none), preconditioning with L pays
-    when k(0) - k(L) > C_BJ(L) / C^it.  Returns (L, {L: total cost in
+    needed on the system preconditioned with L x L blocks (L = 0 for none),
+    preconditioning with L pays when k(0) - k(L) > C_BJ(L) / C^it.  k(L) is
+    either measured (`iters`, {L: k}, e.g. the iteration counts of a
+    BER-parity search) or taken from the classical CG bound for the kappa of
+    that system (`kappas`, {L: kappa}).  Returns (L, {L: total cost in
     iterations}) with the smallest total (the smaller L on a tie).
     `setup_cost(K, L)` gives C_BJ / C^it; the default is the paper's
     multiplication count, a measured ratio of the device's setup and
     iteration times can be passed instead."""
-    total = {L: setup_cost(K, L) + cg_iterations(k, eps) for L, k in kappas.items()}
+    if iters is None:
+        if kappas is None:
+            raise ValueError("pass kappas or iters")
+        iters = {L: cg_iterations(k, eps) for L, k in kappas.items()}
+    total = {L: setup_cost(K, L) + k for L, k in iters.items()}
     best = min(sorted(total), key=lambda L: total[L])
     return best, total
