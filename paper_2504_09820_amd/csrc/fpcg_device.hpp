@@ -253,6 +253,27 @@ template <int S> __device__ __forceinline__ void pair_of(double v, double& lo, d
     lo = __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0));
     hi = __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
 }
+// Value of lane J of each group of four lanes (DPP quad_perm [J, J, J, J],
+// a VALU move with no LDS round trip); J must fold to a constant.
+template <int J> __device__ __forceinline__ uint32_t quad_bcast_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, J * 0x55, 0xF, 0xF, false);
+}
+template <int J> __device__ __forceinline__ float quad_bcast(float v) {
+    return __uint_as_float(quad_bcast_u32<J>(__float_as_uint(v)));
+}
+template <int J> __device__ __forceinline__ double quad_bcast(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = quad_bcast_u32<J>((uint32_t)u), hi = quad_bcast_u32<J>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <typename T> __device__ __forceinline__ T quad_bcast(T v, int j) {
+    switch (j) {
+        case 0: return quad_bcast<0>(v);
+        case 1: return quad_bcast<1>(v);
+        case 2: return quad_bcast<2>(v);
+        default: return quad_bcast<3>(v);
+    }
+}
 template <typename T> __device__ __forceinline__ T col_sum(T v) {
     T lo, hi;
     pair_of<16>(v, lo, hi);

@@ -1331,25 +1331,65 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             acc_t Wr_[NF], Wi_[NF];
 #pragma unroll
             for (int phi = 0; phi < NF; ++phi) { Wr_[phi] = acc_t{0, 0, 0, 0}; Wi_[phi] = acc_t{0, 0, 0, 0}; }
+            if constexpr (FMT == F64) {
+                // FP64: three real products per complex one, Re = P1 - P2 and
+                // Im = P3 - P1 - P2 for P1 = a_r p_r, P2 = a_i p_i,
+                // P3 = (a_r + a_i)(p_r + p_i); P1 and P2 accumulate in Wr_ and Wi_
+                acc_t P3[NF];
 #pragma unroll
-            for (int ws = 0; ws < NW; ++ws) {
+                for (int phi = 0; phi < NF; ++phi) P3[phi] = acc_t{0, 0, 0, 0};
 #pragma unroll
-                for (int kb = 0; kb < NKB; ++kb) {
-                    Wt vr[KPL], vi[KPL];
+                for (int ws = 0; ws < NW; ++ws) {
 #pragma unroll
-                    for (int j = 0; j < KPL; ++j) {
-                        const int e = kb * KPL + j;
-                        if (NW == 1 || ws == wave) { vr[j] = pr[e]; vi[j] = pi[e]; }
-                        else { vr[j] = fetch(ws, e, 0); vi[j] = fetch(ws, e, 1); }
+                    for (int kb = 0; kb < NKB; ++kb) {
+                        Wt vr[KPL], vi[KPL];
+#pragma unroll
+                        for (int j = 0; j < KPL; ++j) {
+                            const int e = kb * KPL + j;
+                            if (NW == 1 || ws == wave) { vr[j] = pr[e]; vi[j] = pi[e]; }
+                            else { vr[j] = fetch(ws, e, 0); vi[j] = fetch(ws, e, 1); }
+                        }
+                        const frag Br = O::pack(vr, sP), Bi = O::pack(vi, sP);
+#pragma unroll
+                        for (int phi = 0; phi < NF; ++phi) {
+                            const frag a_r = A_op(phi, ws, kb, 0), a_i = A_op(phi, ws, kb, 1);
+                            frag a_s = a_r;
+                            asm volatile("" : "+v"(a_s));   // the sum is formed here, not hoisted into registers
+                            Wr_[phi] = O::mfma(a_r, Br, Wr_[phi]);
+                            Wi_[phi] = O::mfma(a_i, Bi, Wi_[phi]);
+                            P3[phi] = O::mfma(a_s + a_i, Br + Bi, P3[phi]);
+                        }
                     }
-                    const frag Br = O::pack(vr, sP), Bi = O::pack(vi, sP), nBi = O::neg(Bi);
+                }
 #pragma unroll
-                    for (int phi = 0; phi < NF; ++phi) {
-                        const frag a_r = A_op(phi, ws, kb, 0), a_i = A_op(phi, ws, kb, 1);
-                        Wr_[phi] = O::mfma(a_r, Br, Wr_[phi]);
-                        Wr_[phi] = O::mfma(a_i, nBi, Wr_[phi]);
-                        Wi_[phi] = O::mfma(a_i, Br, Wi_[phi]);
-                        Wi_[phi] = O::mfma(a_r, Bi, Wi_[phi]);
+                for (int phi = 0; phi < NF; ++phi)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const double p1 = Wr_[phi][jj], p2 = Wi_[phi][jj];
+                        Wr_[phi][jj] = p1 - p2;
+                        Wi_[phi][jj] = (P3[phi][jj] - p1) - p2;
+                    }
+            } else {
+#pragma unroll
+                for (int ws = 0; ws < NW; ++ws) {
+#pragma unroll
+                    for (int kb = 0; kb < NKB; ++kb) {
+                        Wt vr[KPL], vi[KPL];
+#pragma unroll
+                        for (int j = 0; j < KPL; ++j) {
+                            const int e = kb * KPL + j;
+                            if (NW == 1 || ws == wave) { vr[j] = pr[e]; vi[j] = pi[e]; }
+                            else { vr[j] = fetch(ws, e, 0); vi[j] = fetch(ws, e, 1); }
+                        }
+                        const frag Br = O::pack(vr, sP), Bi = O::pack(vi, sP), nBi = O::neg(Bi);
+#pragma unroll
+                        for (int phi = 0; phi < NF; ++phi) {
+                            const frag a_r = A_op(phi, ws, kb, 0), a_i = A_op(phi, ws, kb, 1);
+                            Wr_[phi] = O::mfma(a_r, Br, Wr_[phi]);
+                            Wr_[phi] = O::mfma(a_i, nBi, Wr_[phi]);
+                            Wi_[phi] = O::mfma(a_i, Br, Wi_[phi]);
+                            Wi_[phi] = O::mfma(a_r, Bi, Wi_[phi]);
+                        }
                     }
                 }
             }
@@ -1415,9 +1455,14 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                     for (int e = 0; e < SH; ++e) { sXr[e * NT + tid] = xr_[e]; sXi[e * NT + tid] = xi_[e]; }
                 }
                 if constexpr (NW > 1) __syncthreads();   // x of every wave visible
-                f64x4 Rr[NF], Ri[NF];
+                // three real products per complex one: Re = P1 - P2 and
+                // Im = P3 - P1 - P2 for P1 = a_r x_r, P2 = a_i x_i,
+                // P3 = (a_r + a_i)(x_r + x_i)
+                f64x4 Rr[NF], Ri[NF], R3[NF];
 #pragma unroll
-                for (int phi = 0; phi < NF; ++phi) { Rr[phi] = f64x4{0, 0, 0, 0}; Ri[phi] = f64x4{0, 0, 0, 0}; }
+                for (int phi = 0; phi < NF; ++phi) {
+                    Rr[phi] = f64x4{0, 0, 0, 0}; Ri[phi] = f64x4{0, 0, 0, 0}; R3[phi] = f64x4{0, 0, 0, 0};
+                }
 #pragma unroll
                 for (int ws = 0; ws < NW; ++ws) {
 #pragma unroll
@@ -1431,9 +1476,8 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                             a_at(rowc64(phi), cc, are, aim);
                             const double a_r = (double)are, a_i = (double)aim;
                             Rr[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, bx, Rr[phi], 0, 0, 0);
-                            Rr[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i, by, Rr[phi], 0, 0, 0);
-                            Ri[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, bx, Ri[phi], 0, 0, 0);
-                            Ri[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, by, Ri[phi], 0, 0, 0);
+                            Ri[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, by, Ri[phi], 0, 0, 0);
+                            R3[phi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r + a_i, bx + by, R3[phi], 0, 0, 0);
                         }
                     }
                 }
@@ -1445,8 +1489,9 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                             const int e = 4 * phi + jj;
                             const double b_r = (double)sBr[(base_c + e) * 16 + n];
                             const double b_i = (double)sBi[(base_c + e) * 16 + n];
-                            rr[e] = (Wt)(b_r - Rr[phi][jj]);
-                            ri[e] = (Wt)(b_i - Ri[phi][jj]);
+                            const double p1 = Rr[phi][jj], p2 = Ri[phi][jj];
+                            rr[e] = (Wt)(b_r - (p1 - p2));
+                            ri[e] = (Wt)(b_i - ((R3[phi][jj] - p1) - p2));
                         }
                 }
                 if constexpr (NW > 1) __syncthreads();   // before x changes again

@@ -89,11 +89,11 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
 };
 
 // Register budget in waves per SIMD: three (170 registers) where the build
-// fits without spilling, two for FP64, K = 128, and the FP32 or left-form
-// builds with the FP64 refresh (which keep a second copy of A and M_d).
+// fits without spilling, two for FP64, K = 128, and the left-form builds with
+// the FP64 refresh (which keep a second copy of A and M_d).
 template <int KP, int FMT, int LB, bool SPLIT, bool RFR> constexpr int slab_waves() {
     if (FMT == F64 || KP == 128) return 2;
-    if (RFR && (FMT == F32 || (LB > 0 && !SPLIT))) return 2;
+    if (RFR && LB > 0 && !SPLIT) return 2;
     return 3;
 }
 
@@ -125,7 +125,9 @@ void slab_kernel(const FusedParams P) {
     }
     const int cblk = blockIdx.y;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    // the wave index is uniform over the wave: in a scalar register, its
+    // branches (which tiles a wave owns) are scalar branches
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, n = lane & 15;
     const int col = cblk * 16 + n;
     const bool colv = col < P.R;
@@ -508,7 +510,6 @@ void slab_kernel(const FusedParams P) {
                     t_r[j] = sT[(cbase + cc) * LB + j];
                     t_i[j] = sT[KP * LB + (cbase + cc) * LB + j];
                 }
-                const int q0 = lane & ~3;
 #pragma unroll
                 for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -516,7 +517,7 @@ void slab_kernel(const FusedParams P) {
                         Wt sr = 0, si = 0;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {      // += W[.][j] conj(T[cc][j]), T[cc][j] = 0 for j > cc
-                            const Wt wr = __shfl(vr[f][i], q0 + j), wi = __shfl(vi[f][i], q0 + j);
+                            const Wt wr = quad_bcast(vr[f][i], j), wi = quad_bcast(vi[f][i], j);
                             sr = fma(wr, t_r[j], fma(wi, t_i[j], sr));
                             si = fma(wi, t_r[j], fma(-wr, t_i[j], si));
                         }
@@ -704,18 +705,36 @@ void slab_kernel(const FusedParams P) {
     bool live = true, broken = false;
     for (int it = 1; it <= P.iters; ++it) {
         // ---- varpi = A p   [u_MV]
-        acc_t Wr = acc_t{0, 0, 0, 0}, Wi = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const frag b_r = b_op(par, c, 0), b_i = b_op(par, c, 1);
-            Wr = O::mfma(afr[c][0], b_r, Wr);
-            Wr = O::mfma(afr[c][1], b_i, Wr);
-            Wi = O::mfma(afr[c][0], b_i, Wi);
-            Wi = O::mfma(afr[c][1], neg_op(b_r), Wi);
-        }
         Wt wr[4], wi[4];
+        if constexpr (FMT == F64) {
+            // FP64: three real products per complex one, as in the refresh
+            acc_t P1 = acc_t{0, 0, 0, 0}, P2 = acc_t{0, 0, 0, 0}, P3 = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { wr[e] = (Wt)Wr[e]; wi[e] = (Wt)Wi[e]; }
+            for (int c = 0; c < NCH; ++c) {
+                const frag b_r = b_op(par, c, 0), b_i = b_op(par, c, 1);
+                // (the difference is formed here, not kept: an opaque copy
+                // stops it from being hoisted out of the loop into registers)
+                double a_r = afr[c][0];
+                asm volatile("" : "+v"(a_r));
+                P1 = O::mfma(afr[c][0], b_r, P1);
+                P2 = O::mfma(afr[c][1], b_i, P2);
+                P3 = O::mfma(a_r - afr[c][1], b_r + b_i, P3);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { wr[e] = P1[e] + P2[e]; wi[e] = (P3[e] - P1[e]) + P2[e]; }
+        } else {
+            acc_t Wr = acc_t{0, 0, 0, 0}, Wi = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const frag b_r = b_op(par, c, 0), b_i = b_op(par, c, 1);
+                Wr = O::mfma(afr[c][0], b_r, Wr);
+                Wr = O::mfma(afr[c][1], b_i, Wr);
+                Wi = O::mfma(afr[c][0], b_i, Wi);
+                Wi = O::mfma(afr[c][1], neg_op(b_r), Wi);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { wr[e] = (Wt)Wr[e]; wi[e] = (Wt)Wi[e]; }
+        }
         // ---- phi = p^H varpi, rho_{i-1} (Alg. 3 as printed)  [u_IP]
         const bool need_rp = left && (P.variant == 0);
         Wt v0 = 0, v1 = 0;
@@ -752,28 +771,57 @@ void slab_kernel(const FusedParams P) {
                 sXB[(((size_t)wave * 2 + 1) * 4 + e) * 64 + lane] = xi[e];
             }
             __syncthreads();
-            f64x4 Rr = f64x4{0, 0, 0, 0}, Ri = f64x4{0, 0, 0, 0};
+            // three real products per complex one: with the row of A as
+            // a_r - i a_i, Re = P1 + P2 and Im = P3 + (P2 - P1) for P1 = a_r x_r,
+            // P2 = a_i x_i, P3 = (a_r - a_i)(x_r + x_i); two passes, so that
+            // no more than two accumulators are live at once
+            auto a_of = [&](int c, double& a_r, double& a_i) {
+                const int f = c / 4, k = c % 4;
+                if constexpr (NEED_PERM) { a_r = (double)Acr[f][k]; a_i = (double)Aci[f][k]; }
+                else {
+                    // widened here, from opaque copies, so that A is held in
+                    // u_W and not as hoisted FP64 copies
+                    Wt ar = Apr[RFR ? f : 0][k], ai = Api[RFR ? f : 0][k];
+                    asm volatile("" : "+v"(ar), "+v"(ai));
+                    a_r = (double)ar; a_i = (double)ai;
+                }
+            };
+            auto x_of = [&](int c, int pl) -> double {
+                return (double)sXB[(((size_t)(c / 4) * 2 + pl) * 4 + c % 4) * 64 + lane];
+            };
+            f64x4 P1 = f64x4{0, 0, 0, 0}, P2 = f64x4{0, 0, 0, 0};
 #pragma unroll
             for (int c = 0; c < F * 4; ++c) {
-                const int f = c / 4, k = c % 4;
                 double a_r, a_i;
-                if constexpr (NEED_PERM) { a_r = (double)Acr[f][k]; a_i = (double)Aci[f][k]; }
-                else { a_r = (double)Apr[RFR ? f : 0][k]; a_i = (double)Api[RFR ? f : 0][k]; }
-                const double x_r = (double)sXB[(((size_t)f * 2 + 0) * 4 + k) * 64 + lane];
-                const double x_i = (double)sXB[(((size_t)f * 2 + 1) * 4 + k) * 64 + lane];
-                Rr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, x_r, Rr, 0, 0, 0);
-                Rr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, x_i, Rr, 0, 0, 0);
-                Ri = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, x_i, Ri, 0, 0, 0);
-                Ri = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, -x_r, Ri, 0, 0, 0);
+                a_of(c, a_r, a_i);
+                P1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, x_of(c, 0), P1, 0, 0, 0);
+                P2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, x_of(c, 1), P2, 0, 0, 0);
+            }
+            f64x4 D;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                D[e] = P2[e] - P1[e];
+                Wt be = br_[e];
+                asm volatile("" : "+v"(be));          // converted here, not hoisted out of the loop
+                if (live) rr[e] = (Wt)((double)be - (P1[e] + P2[e]));
+            }
+            f64x4 P3 = f64x4{0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < F * 4; ++c) {
+                double a_r, a_i;
+                a_of(c, a_r, a_i);
+                P3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r - a_i, x_of(c, 0) + x_of(c, 1), P3, 0, 0, 0);
             }
             if (live) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    rr[e] = (Wt)((double)br_[e] - Rr[e]);
-                    ri[e] = (Wt)((double)bi_[e] - Ri[e]);
+                    Wt be = bi_[e];
+                    asm volatile("" : "+v"(be));
+                    ri[e] = (Wt)((double)be - (P3[e] + D[e]));
                 }
             }
-            __syncthreads();                                // x exchange read by every wave
+            // (the x exchange is next written at the next refresh, at least
+            // three barriers later, so no barrier is needed after the reads)
         }
         // ---- z = M r (left form) or r, rho_i, beta, p
         Wt zr[4], zi[4];
