@@ -1354,7 +1354,7 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
                         for (int phi = 0; phi < NF; ++phi) {
                             const frag a_r = A_op(phi, ws, kb, 0), a_i = A_op(phi, ws, kb, 1);
                             frag a_s = a_r;
-                            asm volatile("" : "+v"(a_s));   // the sum is formed here, not hoisted into registers
+                            asm("" : "+v"(a_s) : "s"(it));  // the sum is formed here, not hoisted into registers
                             Wr_[phi] = O::mfma(a_r, Br, Wr_[phi]);
                             Wi_[phi] = O::mfma(a_i, Bi, Wi_[phi]);
                             P3[phi] = O::mfma(a_s + a_i, Br + Bi, P3[phi]);

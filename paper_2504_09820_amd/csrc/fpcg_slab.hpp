@@ -712,10 +712,11 @@ void slab_kernel(const FusedParams P) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const frag b_r = b_op(par, c, 0), b_i = b_op(par, c, 1);
-                // (the difference is formed here, not kept: an opaque copy
-                // stops it from being hoisted out of the loop into registers)
+                // (the difference is formed here, not kept: a copy that
+                // depends on the iteration cannot be hoisted out of the loop
+                // into registers, and, not volatile, does not order the loads)
                 double a_r = afr[c][0];
-                asm volatile("" : "+v"(a_r));
+                asm("" : "+v"(a_r) : "s"(it));
                 P1 = O::mfma(afr[c][0], b_r, P1);
                 P2 = O::mfma(afr[c][1], b_i, P2);
                 P3 = O::mfma(a_r - afr[c][1], b_r + b_i, P3);
@@ -779,10 +780,10 @@ void slab_kernel(const FusedParams P) {
                 const int f = c / 4, k = c % 4;
                 if constexpr (NEED_PERM) { a_r = (double)Acr[f][k]; a_i = (double)Aci[f][k]; }
                 else {
-                    // widened here, from opaque copies, so that A is held in
-                    // u_W and not as hoisted FP64 copies
+                    // widened here, from copies that depend on the iteration,
+                    // so that A is held in u_W and not as hoisted FP64 copies
                     Wt ar = Apr[RFR ? f : 0][k], ai = Api[RFR ? f : 0][k];
-                    asm volatile("" : "+v"(ar), "+v"(ai));
+                    asm("" : "+v"(ar), "+v"(ai) : "s"(it));
                     a_r = (double)ar; a_i = (double)ai;
                 }
             };
@@ -802,7 +803,7 @@ void slab_kernel(const FusedParams P) {
             for (int e = 0; e < 4; ++e) {
                 D[e] = P2[e] - P1[e];
                 Wt be = br_[e];
-                asm volatile("" : "+v"(be));          // converted here, not hoisted out of the loop
+                asm("" : "+v"(be) : "s"(it));         // converted here, not hoisted out of the loop
                 if (live) rr[e] = (Wt)((double)be - (P1[e] + P2[e]));
             }
             f64x4 P3 = f64x4{0, 0, 0, 0};
@@ -816,7 +817,7 @@ void slab_kernel(const FusedParams P) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     Wt be = bi_[e];
-                    asm volatile("" : "+v"(be));
+                    asm("" : "+v"(be) : "s"(it));
                     ri[e] = (Wt)((double)be - (P3[e] + D[e]));
                 }
             }
