@@ -838,7 +838,10 @@ def profile_run(args):
     s2 = torch.full((B,), W.sigma2_from_snr_db(c["snr_db"], Nbs, "paper"), dtype=torch.float64, device=dev)
     ctx = fp.Context(0)
     form = "fused"
-    if not args.no_tune:
+    if args.form:
+        form = args.form
+        ctx.set_launch_form(form)
+    elif not args.no_tune:
         form = ctx.autotune(B, Nbs, K, R, q, it, cd["L"], cd["sched"], cd["refresh"], cd["refine"], cd["variant"], reps=2)
     out = (torch.empty((B, K, R), dtype=torch.complex64, device=dev), torch.empty((B, K, R), dtype=torch.uint8, device=dev),
            torch.empty((B,), dtype=torch.int32, device=dev))
@@ -1022,7 +1025,18 @@ def batch_bench(args):
         cd["p50_ms"] = float(np.median(per))
         log(f"  {cd['sched']} L={cd['L']} refresh={cd['refresh']} refine={cd['refine']} v{cd['variant']}: "
             f"I={cd['iters']} BER {cd['ber']:.2e}, kernel p50 {cd['p50_ms']:.4f} ms ({cd['form']})")
-    best = min(cands, key=lambda d: d["p50_ms"])
+    # the headline: the fastest configured schedule that reaches BER parity;
+    # where none does, the heuristic's pick if it does
+    reached = [cd for cd in cands if cd.get("parity_reached") is not False]
+    source = "configured"
+    if reached:
+        best = min(reached, key=lambda d: d["p50_ms"])
+    elif heur_cd and heur_cd.get("parity_reached") is not False:
+        best = heur_cd
+        source = "heuristic (no configured schedule reaches BER parity)"
+    else:
+        best = min(cands, key=lambda d: d["p50_ms"])
+        source = "configured (BER parity not reached)"
     form64 = tune(F64, I64)
     # Remark 4's break-even rule on the measured (BER-parity) iteration counts
     # of the configured block sizes of one format
@@ -1056,9 +1070,13 @@ def batch_bench(args):
     log(f"{best['sched']} L={best['L']}: {ms_step:.4f} ms/step wall, kernel p50 {np.median(per_mp):.4f} ms, "
         f"{value:.4e} detections/s")
     steps64 = max(5, args.steps // 4)
-    wall_64, per_64 = graph_timed(launcher(F64, I64), steps64, 2, IDLE_S)
-    torch.cuda.synchronize()
-    x_64 = xo.clone()
+    if best["sched"] == "fp64" and best["L"] == 0 and best["iters"] == I64 and not best["refresh"] and not best["refine"]:
+        # the timed schedule is FP64 CG itself (c1): one measurement serves both
+        steps64, wall_64, per_64, x_64 = args.steps, wall_mp, per_mp, x_mp
+    else:
+        wall_64, per_64 = graph_timed(launcher(F64, I64), steps64, 2, IDLE_S)
+        torch.cuda.synchronize()
+        x_64 = xo.clone()
     value64 = B * R / (wall_64 / steps64)
     log(f"fp64 CG: {wall_64 / steps64 * 1e3:.4f} ms/step, {value64:.4e} detections/s")
     heur_line = None
@@ -1139,7 +1157,8 @@ def batch_bench(args):
                    "schedule": best["sched"], "block_L": best["L"], "variant": best["variant"],
                    "refresh_every": best["refresh"], "refine_steps": best["refine"], "iters": best["iters"],
                    "launch_form": best["form"], "fp64_iters": I64, "fp64_launch_form": form64,
-                   "io": "complex64" if io == np.complex64 else "complex128", "timing": "warm HIP graph replays"},
+                   "io": "complex64" if io == np.complex64 else "complex128", "timing": "warm HIP graph replays",
+                   "schedule_source": source},
         "latency_ms": {"p50": round(float(np.median(per_mp)), 5), "p99": round(float(np.quantile(per_mp, 0.99)), 5),
                        "kernel_mean": round(kern_ms, 5)},
         "algorithmic_bytes_per_launch": work["bytes"],
@@ -1178,6 +1197,8 @@ def main():
     ap.add_argument("--refresh", type=int, default=0, help="FP64 refresh period (explicit --schedule only)")
     ap.add_argument("--refine", type=int, default=0, help="FP64 refinement steps (explicit --schedule only)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-form autotuner (fused, default waves)")
+    ap.add_argument("--form", default="", help="with --profile: this launch form (fused, fused-wN, pipelined, slab) "
+                                               "instead of the autotuner's")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="seconds of oracle work per host process")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",

@@ -131,6 +131,10 @@ fpcg_status fpcg_tune_table(const fpcg_ctx* ctx, char* buf, size_t cap, size_t* 
  * gathered and solved with FP64 CG for min(K, 32) steps with the kappa output
  * of fpcg_detect_ex, and *kappa receives the mean of the estimates (a lower
  * estimate of each channel's kappa, exact in exact arithmetic when K <= 32).
+ * Where no FP64 build serves (K, block_L) (K = 128 with block_L = 16), the
+ * solve runs in the most precise built format (FP32 work; the symmetric form,
+ * else the textbook left form of Alg. 3), whose coefficients estimate the
+ * same spectrum less accurately.
  * Both record the value in the context for the NULL schedule of
  * fpcg_detect.  fpcg_expected_kappa allocates and frees its own device
  * buffers and synchronises `stream`; FPCG_E_INVAL for bad sizes or NULL

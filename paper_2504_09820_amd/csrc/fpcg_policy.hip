@@ -246,10 +246,28 @@ fpcg_status fpcg_expected_kappa(fpcg_ctx* ctx, void* stream, int64_t B, int32_t 
     if (!ctx || !kappa) return fail(FPCG_E_INVAL, "ctx and kappa must be non-NULL");
     if (B < 1 || n_sample < 1) return fail(FPCG_E_INVAL, "B=%lld and n_sample=%d must be >= 1", (long long)B, n_sample);
     if (!H || !Y || !sigma2) return fail(FPCG_E_INVAL, "H, Y and sigma2 must be non-NULL");
-    // FP64 iterations over the whole Krylov space the estimate can use
+    // FP64 iterations over the whole Krylov space the estimate can use; where
+    // no FP64 build exists for the class, the most precise built format
+    // (symmetric form, else the textbook left form of Alg. 3, whose
+    // coefficients are those of the Lanczos process of M_d A)
     const int32_t iters = std::min<int32_t>(K, 32);
-    const fpcg_schedule f64 = {FPCG_F64, FPCG_F64, FPCG_F64, FPCG_F64, 0, 0, block_L > 0 ? 2 : 0};
+    fpcg_schedule f64 = {FPCG_F64, FPCG_F64, FPCG_F64, FPCG_F64, 0, 0, block_L > 0 ? 2 : 0};
     fpcg_status st = check_args(B, Nbs, K, R, 4, iters, block_L, &f64, nullptr);
+    if (st == FPCG_E_UNSUPPORTED) {
+        static const int32_t fmts[] = {FPCG_F32, FPCG_F16, FPCG_BF16};
+        for (int32_t f : fmts) {
+            for (int32_t v : {2, 1}) {
+                const fpcg_schedule c = {f, f, FPCG_F32, FPCG_F32, 0, 0, block_L > 0 ? v : 0};
+                if (check_args(B, Nbs, K, R, 4, iters, block_L, &c, nullptr) == FPCG_OK) {
+                    f64 = c;
+                    st = FPCG_OK;
+                    break;
+                }
+            }
+            if (st == FPCG_OK) break;
+        }
+        if (st == FPCG_OK) clear_error();
+    }
     if (st != FPCG_OK) return st;
     const int64_t n = std::min<int64_t>(n_sample, B);
     const size_t el = io_c64 ? 8 : 16;

@@ -74,8 +74,8 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
     // every wave loads every slab (FP64, bound by its matrix-core rate, where
     // the exchange measured slower)
     static constexpr bool STAGE = FMT != F64;
-    // H staged per loaded block: [2 buffers][slab][instruction][plane][lane] operand fragments
-    static constexpr size_t sz_hstage = STAGE ? 2 * (size_t)F * NSUB * 2 * 64 * sizeof(typename Op<FMT, KPLG>::frag) : 0;
+    // H staged per loaded block: [2 buffers][slab][instruction][re, im, -im][lane] operand fragments
+    static constexpr size_t sz_hstage = STAGE ? 2 * (size_t)F * NSUB * 3 * 64 * sizeof(typename Op<FMT, KPLG>::frag) : 0;
     __host__ __device__ static constexpr size_t sz_main(size_t es, bool refresh) {
         size_t a = sz_tiles > sz_hstage ? sz_tiles : sz_hstage, b = sz_pb + (refresh ? sz_xb : 0), c = sz_stage(es);
         return a > b ? (a > c ? a : c) : (b > c ? b : c);
@@ -218,62 +218,70 @@ void slab_kernel(const FusedParams P) {
                 }
             }
         };
-        gfrag* sStage = reinterpret_cast<gfrag*>(smain);                 // [2][F][NSUB][2][64]
-        auto st_at = [&](int buf, int f, int u, int pl) -> int { return (((buf * F + f) * NSUB + u) * 2 + pl) * 64 + lane; };
+        gfrag* sStage = reinterpret_cast<gfrag*>(smain);                 // [2][F][NSUB][3][64]
+        auto st_at = [&](int buf, int f, int u, int pl) -> int { return (((buf * F + f) * NSUB + u) * 3 + pl) * 64 + lane; };
         Wt hr[NLD], hi[NLD], yr[NLD], yi[NLD];        // the block in flight
         auto gram_loop = [&](auto hcp) {
+            // per-lane parts of the offsets once; the block's and the row's
+            // parts are uniform (scalar), one vector add per load
+            const uint32_t hbase = hl + (uint32_t)(g * NLD) * hrow, ybase = yl + (uint32_t)(g * NLD) * yrow;
             auto load_block = [&](int a0) {
-                const uint32_t ab = (uint32_t)(a0 + g * NLD);
+                const uint32_t ha = (uint32_t)a0 * hrow, ya = (uint32_t)a0 * yrow;
 #pragma unroll
                 for (int j = 0; j < NLD; ++j) {
-                    CxB<IOT>::template load<decltype(hcp)::value>(bH, hl + (ab + j) * hrow, hr[j], hi[j]);
-                    CxB<IOT>::load(bY, yl + (ab + j) * yrow, yr[j], yi[j]);
+                    CxB<IOT>::template load<decltype(hcp)::value>(bH, hbase + (ha + (uint32_t)j * hrow), hr[j], hi[j]);
+                    CxB<IOT>::load(bY, ybase + (ya + (uint32_t)j * yrow), yr[j], yi[j]);
                 }
             };
             const int nblk = (Nbs + KBG - 1) / KBG;
             load_block(0);
             for (int b = 0; b < nblk; ++b) {
                 const int buf = b & 1;
-                gfrag Wr_[NSUB], Wi_[NSUB], Yr[NSUB], Yi[NSUB];
+                gfrag Wr_[NSUB], Wi_[NSUB], nWi_[NSUB], Yr[NSUB], Yi[NSUB];
 #pragma unroll
                 for (int u = 0; u < NSUB; ++u) {
                     Wr_[u] = OG::pack(&hr[u * KPLG], 1.f);
                     Wi_[u] = OG::pack(&hi[u * KPLG], 1.f);
+                    nWi_[u] = OG::neg(Wi_[u]);
                     Yr[u] = OG::pack(&yr[u * KPLG], 1.f);
                     Yi[u] = OG::pack(&yi[u * KPLG], 1.f);
                     sStage[st_at(buf, wave, u, 0)] = Wr_[u];
                     sStage[st_at(buf, wave, u, 1)] = Wi_[u];
+                    sStage[st_at(buf, wave, u, 2)] = nWi_[u];
+                    // Y rounded here, so its registers are free for the next
+                    // block's loads (not kept alive beside them)
+                    asm volatile("" ::"v"(Yr[u]), "v"(Yi[u]));
                 }
                 __syncthreads();                      // every slab of this block published
                 if (b + 1 < nblk) load_block((b + 1) * KBG);
 #pragma unroll
                 for (int u = 0; u < NSUB; ++u) {
-                    gfrag Xr[F], Xi[F], nXi[F];
+                    // this wave's tiles q = s NW + wave (slot s), decoded to
+                    // their slab pair in scalar registers; operands read
+                    // from LDS per tile
 #pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        Xr[f] = sStage[st_at(buf, f, u, 0)];
-                        Xi[f] = sStage[st_at(buf, f, u, 1)];
-                        nXi[f] = OG::neg(Xi[f]);
-                    }
-                    int q = 0;
+                    for (int s = 0; s < PPW; ++s) {
+                        const int q = s * NW + wave;
+                        if (q < C::NTILE) {
+                            int f1 = 0;
 #pragma unroll
-                    for (int f1 = 0; f1 < F; ++f1)
-#pragma unroll
-                        for (int f2 = f1; f2 < F; ++f2) {
-                            if (q % NW == wave) {
-                                const int s = q / NW;
-                                gAr[s] = OG::mfma(Xr[f1], Xr[f2], gAr[s]);
-                                gAr[s] = OG::mfma(Xi[f1], Xi[f2], gAr[s]);
-                                gAi[s] = OG::mfma(Xr[f1], Xi[f2], gAi[s]);
-                                gAi[s] = OG::mfma(nXi[f1], Xr[f2], gAi[s]);
-                            }
-                            ++q;
+                            for (int i = 1; i < F; ++i)
+                                if (q >= tile_index(i, i, F)) f1 = i;
+                            const int f2 = f1 + (q - tile_index(f1, f1, F));
+                            const gfrag x1r = sStage[st_at(buf, f1, u, 0)], x1i = sStage[st_at(buf, f1, u, 1)];
+                            const gfrag nx1i = sStage[st_at(buf, f1, u, 2)];
+                            const gfrag x2r = sStage[st_at(buf, f2, u, 0)], x2i = sStage[st_at(buf, f2, u, 1)];
+                            gAr[s] = OG::mfma(x1r, x2r, gAr[s]);
+                            gAr[s] = OG::mfma(x1i, x2i, gAr[s]);
+                            gAi[s] = OG::mfma(x1r, x2i, gAi[s]);
+                            gAi[s] = OG::mfma(nx1i, x2r, gAi[s]);
                         }
+                    }
                     // matched filter tile of this wave's slab
                     gBr = OG::mfma(Wr_[u], Yr[u], gBr);
                     gBr = OG::mfma(Wi_[u], Yi[u], gBr);
                     gBi = OG::mfma(Wr_[u], Yi[u], gBi);
-                    gBi = OG::mfma(OG::neg(Wi_[u]), Yr[u], gBi);
+                    gBi = OG::mfma(nWi_[u], Yr[u], gBi);
                 }
             }
             __syncthreads();                          // the stage is read before the tiles overwrite it

@@ -63,12 +63,13 @@ def test_gram_matches_oracle(sched, K, Nbs, R, io):
     assert not fl.cpu().numpy().any()
 
 
-@pytest.mark.parametrize("K,Nbs,L,zeta", [(32, 128, 0, 0.5), (32, 128, 8, 0.8), (64, 256, 4, 0.7)])
+@pytest.mark.parametrize("K,Nbs,L,zeta", [(32, 128, 0, 0.5), (32, 128, 8, 0.8), (64, 256, 4, 0.7), (128, 512, 16, 0.9)])
 def test_expected_kappa_against_spectrum(K, Nbs, L, zeta):
     """E{kappa} from the device (FP64 CG coefficients, min(K, 32) steps):
     at K <= 32 the Krylov space is full and the mean equals the exact
     E{kappa} of the oracle's eigenvalues; at K = 64 it is a lower estimate
-    within 15 %."""
+    within 15 %.  K = 128 with L = 16 has no FP64 build: the estimate comes
+    from the fp16 left form (FP32 work), a lower estimate within a factor 2."""
     import torch
 
     import paper_2504_09820_amd as fp
@@ -83,8 +84,10 @@ def test_expected_kappa_against_spectrum(K, Nbs, L, zeta):
     print(f"  device {k_dev:.4f}  exact {k_ex:.4f}", flush=True)
     if K <= 32:
         assert abs(k_dev / k_ex - 1) < 1e-2
-    else:
+    elif K == 64:
         assert 0.85 * k_ex <= k_dev <= k_ex * (1 + 1e-3)
+    else:
+        assert 0.5 * k_ex <= k_dev <= k_ex * 1.05
     tab = json.loads(ctx.tune_table())
     assert {"Nbs": Nbs, "K": K, "L": L, "kappa": k_dev} in tab["kappa"]
     ctx.close()
