@@ -294,6 +294,32 @@ fpcg_status fpcg_detect_ex_static(fpcg_ctx* ctx, void* stream,
                                   void* xhat, uint8_t* labels, uint32_t* flags,
                                   const int32_t* chan_idx, int64_t n_idx, float* kappa, float* gain);
 
+/* The block-Jacobi preconditioner (eq. pre_BJ) kept across calls.  As
+ * fpcg_detect, with block_L > 0 and `precond` a device array of B * K *
+ * block_L complex values in the work precision (complex64 for u_W = FP32,
+ * complex128 for FP64), caller-owned: element [b][k][j] is entry (k mod L, j)
+ * of T_i = C_i^{-1} for the L-block i holding row k of channel b, C_i C_i^H
+ * the i-th diagonal block of that channel's u_W Gram.
+ *   mode FPCG_PRECOND_STORE: T is computed as fpcg_detect computes it and
+ *     written to `precond` (the results are bitwise those of fpcg_detect);
+ *   mode FPCG_PRECOND_LOAD: T is read from `precond` in place of the block
+ *     factorisation, and the iteration uses M_d = T^H T (left form) or
+ *     T A T^H (symmetric form) of that T: a factor stored for the same
+ *     channels (a resident channel set) or for an earlier realisation of
+ *     them (a time-varying channel, Sec. V).  No BLOCK_NOT_PD flag then.
+ * Channels whose K is padded keep the identity on the padding.  Runs the
+ * fused or slab form (FPCG_LAUNCH_PIPELINED runs fused).  FPCG_E_INVAL for
+ * block_L = 0, a NULL precond with B > 0, or another mode. */
+#define FPCG_PRECOND_STORE 1
+#define FPCG_PRECOND_LOAD 2
+fpcg_status fpcg_detect_pc(fpcg_ctx* ctx, void* stream,
+                           int64_t B, int32_t Nbs, int32_t K, int32_t R,
+                           const void* H, const void* Y, int32_t io_c64, const double* sigma2,
+                           int32_t qam_order, int32_t iters, int32_t block_L,
+                           const fpcg_schedule* sched,
+                           void* xhat, uint8_t* labels, uint32_t* flags,
+                           void* precond, int32_t mode);
+
 /* Step a0-a1 on its own (Sec. II, eq. inversion): the Gram A = H^H H +
  * sigma^2 I and the matched filter B = H^H Y of every channel, formed exactly
  * as fpcg_detect forms them for `sched` (H and Y rounded to sched->gram_op,

@@ -709,11 +709,16 @@ class Result:
     b: np.ndarray          # matched filter in u_W
 
 
-def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64, coeffs=None) -> Result:
+def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64, coeffs=None, T_given=None) -> Result:
     """Gram + matched filter -> (BJ setup) -> (P)CG -> (refinement) -> slicer.
 
     ``coeffs``, if a list, receives the CG coefficients of the first solve
-    (the one of b; see fp_cg)."""
+    (the one of b; see fp_cg).  ``T_given`` (B, K, K), if set with L > 0,
+    is the block-Jacobi factor T = blockdiag(C_i^{-1}) used in place of the
+    factorisation of this A: a factor kept from earlier channel realisations
+    (Sec. V, time-varying channel; eq. pre_BJ with the stored factor).  The
+    preconditioner is then M_d = T^H T (formed in FP64, rounded once to u_W)
+    or the symmetric form's T A T^H, and no block is flagged."""
     H = np.asarray(H, dtype=np.complex128)
     Y = np.asarray(Y, dtype=np.complex128)
     Bn = H.shape[0]
@@ -724,11 +729,17 @@ def detect(H, Y, sigma2, q: int, iters: int, L: int = 0, sched: Schedule = FP64,
     M = T = Abar = None
     split = bool(L) and sched.variant == 2
     if L:
-        if split:
+        if T_given is not None:
+            T = np.asarray(T_given, dtype=np.complex128)
+            not_pd = np.zeros(Bn, dtype=bool)
+            if not split:
+                M = fl(np.conj(np.swapaxes(T, -1, -2)) @ T, sched.work)
+        elif split:
             T, not_pd = bj_factor(A, L, sched.work)
-            Abar = split_system(A, T, sched.work)
         else:
             M, not_pd = bj_inverse(A, L, sched.work)
+        if split:
+            Abar = split_system(A, T, sched.work)
         flags |= np.where(not_pd, FLAG_BLOCK_NOT_PD, 0).astype(np.uint32)
     mv = MatVec(Abar if split else A, sched, flags)
 

@@ -28,6 +28,7 @@ FMT_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16", 4: "fp8"}
 FLAGS = {"nonfinite": 1, "breakdown": 2, "block_not_pd": 4, "fp8_sat": 8}
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5
+PRECOND_STORE, PRECOND_LOAD = 1, 2
 
 
 class FpcgError(RuntimeError):
@@ -114,6 +115,8 @@ def lib():
     L.fpcg_detect_ex.restype = st
     L.fpcg_detect_ex_static.argtypes = L.fpcg_detect_ex.argtypes
     L.fpcg_detect_ex_static.restype = st
+    L.fpcg_detect_pc.argtypes = L.fpcg_detect.argtypes + [vp, i32]
+    L.fpcg_detect_pc.restype = st
     L.fpcg_gram.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, i32, vp, ctypes.POINTER(Schedule), vp, vp, vp]
     L.fpcg_gram.restype = st
     L.fpcg_demap_maxlog.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp]
@@ -296,7 +299,7 @@ def _check_tensor(t, name, shape, dtype, device):
 def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Schedule" = "fp64",
            refresh_every: int = 0, refine_steps: int = 0, variant: int = 0,
            ctx: Optional[Context] = None, stream=None, out=None, chan_idx=None, kappa=None, gain=None,
-           static_workspace: bool = False):
+           static_workspace: bool = False, precond=None, precond_mode: Optional[str] = None):
     """Run the detector on device tensors.
 
     H (B, Nbs, K) and Y (B, Nbs, R): complex64 or complex128 CUDA tensors,
@@ -309,7 +312,11 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
     runs such launches through fpcg_detect_ex_static, which allocates
     nothing (its workspace is a fixed per-GPU array; calls that overlap on
     one GPU race).  schedule_=None runs the precision heuristic's format for
-    the context's E{kappa} of the workload class.
+    the context's E{kappa} of the workload class.  precond (complex64 CUDA
+    tensor (B, K, L) for FP32 work, complex128 for "fp64") keeps the
+    block-Jacobi factor T across calls (fpcg_detect_pc): precond_mode
+    "store" writes the factor this launch computes, "load" uses the given
+    one in place of the block factorisation.
     """
     import torch
 
@@ -343,6 +350,21 @@ def detect(H, Y, sigma2, qam: int, iters: int, L: int = 0, schedule_: "str | Sch
         _check_tensor(xhat, "xhat", (B, K, R), H.dtype, H.device)
         _check_tensor(labels, "labels", (B, K, R), torch.uint8, H.device)
         _check_tensor(flags, "flags", (B,), torch.int32, H.device)
+    if precond is not None or precond_mode is not None:
+        if chan_idx is not None or kappa is not None or gain is not None or static_workspace:
+            raise ValueError("precond does not combine with chan_idx, kappa, gain or static_workspace")
+        if precond_mode not in ("store", "load") or precond is None or L <= 0 or sched is None:
+            raise ValueError("precond needs L > 0, a schedule, a tensor and precond_mode 'store' or 'load'")
+        work64 = sched is not None and sched.work == FMT["fp64"]
+        _check_tensor(precond, "precond", (B, K, L), torch.complex128 if work64 else torch.complex64, H.device)
+        _check(lib().fpcg_detect_pc(ctx.handle, _stream_handle(stream, H.device), B, Nbs, K, R,
+                                    ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                    1 if H.dtype == torch.complex64 else 0, ctypes.c_void_p(sigma2.data_ptr()),
+                                    qam, iters, L, ctypes.byref(sched) if sched is not None else None,
+                                    ctypes.c_void_p(xhat.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                                    ctypes.c_void_p(flags.data_ptr()), ctypes.c_void_p(precond.data_ptr()),
+                                    PRECOND_STORE if precond_mode == "store" else PRECOND_LOAD))
+        return xhat, labels, flags
     if chan_idx is not None or kappa is not None or gain is not None or static_workspace:
         if chan_idx is not None:
             if chan_idx.dtype != torch.int32 or not chan_idx.is_cuda or chan_idx.device != H.device:

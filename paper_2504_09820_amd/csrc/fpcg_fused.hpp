@@ -69,6 +69,13 @@ struct FusedParams {
     // then ends there (no solve, no x_hat or labels; flags of step 1 only)
     void* gram_out;
     void* mf_out;
+    // optional: the block-Jacobi factor T = C^{-1} of eq. pre_BJ (C the
+    // Cholesky factor of each diagonal block of the u_W Gram), per channel
+    // [row k][column j of its L-block] interleaved complex in u_W: written
+    // after the setup (T_out), or read in place of the block factorisation
+    // (T_in, e.g. the factor of an earlier channel realisation)
+    void* T_out;
+    const void* T_in;
 };
 
 // Lanes of the symmetric block-Jacobi transform.  Pass 1 (rows) needs rows
@@ -661,7 +668,18 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
         Wt diag = 0;                                  // a_ii, for the not-PD fallback
         bool blk_bad = false;
         Wt tr[LB], ti[LB];
-        if constexpr (LB <= 8) {
+        // a given factor (T_in, uniform) replaces the factorisation
+        const bool factor = MODE != MODE_FULL || !P.T_in;
+        if (!factor) {
+            if (act && cb < K) {
+                const Wt* tin = static_cast<const Wt*>(P.T_in) + ((size_t)ch * K + cb) * LB * 2;
+#pragma unroll
+                for (int r = 0; r < LB; ++r) { tr[r] = tin[(r * LB + i) * 2]; ti[r] = tin[(r * LB + i) * 2 + 1]; }
+            } else {                                  // padding blocks: the identity
+#pragma unroll
+                for (int r = 0; r < LB; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
+            }
+        } else if constexpr (LB <= 8) {
         Wt cr[LB][LB], ci[LB][LB];
 #pragma unroll
         for (int r = 0; r < LB; ++r)
@@ -775,6 +793,13 @@ __device__ __forceinline__ void detect_channel(const FusedParams& P, const int64
             for (int r = 0; r < LB; ++r) {
                 dTr[(cb + r) * LB + i] = tr[r];
                 dTi[(cb + r) * LB + i] = ti[r];
+            }
+            if constexpr (MODE == MODE_FULL) {
+                if (P.T_out && cblk == 0 && cb < K) {  // column i of this block of T
+                    Wt* tout = static_cast<Wt*>(P.T_out) + ((size_t)ch * K + cb) * LB * 2;
+#pragma unroll
+                    for (int r = 0; r < LB; ++r) { tout[(r * LB + i) * 2] = tr[r]; tout[(r * LB + i) * 2 + 1] = ti[r]; }
+                }
             }
             if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
             if constexpr (MODE == MODE_FULL) {

@@ -342,6 +342,8 @@ fpcg_status launch_detect_form(const fpcg_ctx* ctx, hipStream_t stream, const Pl
     p.gain = ex ? ex->gain : nullptr;
     p.gram_out = ex ? ex->gram_out : nullptr;
     p.mf_out = ex ? ex->mf_out : nullptr;
+    p.T_out = ex ? ex->T_out : nullptr;
+    p.T_in = ex ? ex->T_in : nullptr;
     const int ncb = (R + 15) / 16;
     if (e->kind == 1) {
         dim3 grid((unsigned)n, (unsigned)((R + 15) / 16));
@@ -567,6 +569,38 @@ fpcg_status fpcg_detect_ex_static(fpcg_ctx* ctx, void* stream, int64_t B, int32_
                                   int64_t n_idx, float* kappa, float* gain) {
     return detect_ex_impl(ctx, stream, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order, iters, block_L, sched, xhat,
                           labels, flags, chan_idx, n_idx, kappa, gain, true);
+}
+
+fpcg_status fpcg_detect_pc(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,
+                           const void* Y, int32_t io_c64, const double* sigma2, int32_t qam_order, int32_t iters,
+                           int32_t block_L, const fpcg_schedule* sched, void* xhat, uint8_t* labels, uint32_t* flags,
+                           void* precond, int32_t mode) {
+    clear_error();
+    if (mode != FPCG_PRECOND_STORE && mode != FPCG_PRECOND_LOAD)
+        return fail(FPCG_E_INVAL, "precond mode %d (FPCG_PRECOND_STORE or FPCG_PRECOND_LOAD)", mode);
+    if (block_L <= 0) return fail(FPCG_E_INVAL, "a kept preconditioner needs block_L > 0");
+    if (!ctx) return fail(FPCG_E_INVAL, "ctx is NULL");
+    fpcg_schedule rs;
+    fpcg_status st = resolve_schedule(ctx, B, Nbs, K, R, qam_order, iters, block_L, sched, &rs);
+    if (st != FPCG_OK) return st;
+    Plan plan;
+    st = check_args(B, Nbs, K, R, qam_order, iters, block_L, &rs, &plan);
+    if (st != FPCG_OK) return st;
+    if (B > 0 && (!H || !Y || !sigma2 || !xhat || !labels || !precond))
+        return fail(FPCG_E_INVAL, "H, Y, sigma2, xhat, labels and precond must be non-NULL");
+    if (B == 0) return FPCG_OK;
+    ScopedDevice sd(ctx->device);
+    LaunchExtra ex;
+    ex.n = B;
+    if (mode == FPCG_PRECOND_STORE) ex.T_out = precond;
+    else ex.T_in = precond;
+    int form = ctx->launch_form;
+    if (form == FPCG_LAUNCH_AUTO) {
+        auto it = ctx->tuned.find(tune_key(plan, R, io_c64));
+        form = it != ctx->tuned.end() ? it->second : FPCG_LAUNCH_FUSED;
+    }
+    return launch_detect_form(ctx, (hipStream_t)stream, plan, form, B, Nbs, K, R, H, Y, io_c64, sigma2, qam_order,
+                              iters, xhat, labels, flags, &ex);
 }
 
 fpcg_status fpcg_gram(fpcg_ctx* ctx, void* stream, int64_t B, int32_t Nbs, int32_t K, int32_t R, const void* H,

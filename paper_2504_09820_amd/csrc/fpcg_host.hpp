@@ -60,6 +60,8 @@ struct LaunchExtra {
     float* gain = nullptr;
     void* gram_out = nullptr;    // step 1 only: the Gram and matched filter in u_W
     void* mf_out = nullptr;
+    void* T_out = nullptr;       // the block-Jacobi factor, written / read in place of its factorisation
+    const void* T_in = nullptr;
 };
 // one launch in the given form (FPCG_LAUNCH_FUSED or FPCG_LAUNCH_PIPELINED;
 // a launch with extras always runs fused)

@@ -394,51 +394,62 @@ void slab_kernel(const FusedParams P) {
             const bool act = tid < KP;
             const int t = act ? tid : 0;
             const int i = t % LB, cb = t - i;
-            Wt cr[LB][LB], ci[LB][LB];
-#pragma unroll
-            for (int r = 0; r < LB; ++r)
-#pragma unroll
-                for (int c = 0; c <= r; ++c) { cr[r][c] = sD[(cb + r) * LB + c]; ci[r][c] = sD[KP * LB + (cb + r) * LB + c]; }
-            Wt diag = 0;
-#pragma unroll
-            for (int r = 0; r < LB; ++r)
-                if (r == i) diag = cr[r][r];
-            bool blk_bad = false;
-#pragma unroll
-            for (int j = 0; j < LB; ++j) {
-                Wt d = cr[j][j];
-                if (!(d > 0) || !__builtin_isfinite(d)) { blk_bad = true; d = 1; }
-                const Wt l = sqrt(d), inv = (Wt)1 / l;
-                cr[j][j] = l;
-                ci[j][j] = inv;
-#pragma unroll
-                for (int r = j + 1; r < LB; ++r) { cr[r][j] = cr[r][j] * inv; ci[r][j] = ci[r][j] * inv; }
-#pragma unroll
-                for (int r = j + 1; r < LB; ++r)
-#pragma unroll
-                    for (int c = j + 1; c <= r; ++c) {
-                        cr[r][c] = fma(-cr[r][j], cr[c][j], fma(-ci[r][j], ci[c][j], cr[r][c]));
-                        ci[r][c] = fma(-ci[r][j], cr[c][j], fma(cr[r][j], ci[c][j], ci[r][c]));
-                    }
-            }
             Wt tr[LB], ti[LB];
+            bool blk_bad = false;
+            if (P.T_in) {                             // a given factor replaces the factorisation
+                if (act && cb < K) {
+                    const Wt* tin = static_cast<const Wt*>(P.T_in) + ((size_t)ch * K + cb) * LB * 2;
 #pragma unroll
-            for (int r = 0; r < LB; ++r) {
-                const Wt inv_rr = ci[r][r];
-                Wt sr = 0, si = 0;
+                    for (int r = 0; r < LB; ++r) { tr[r] = tin[(r * LB + i) * 2]; ti[r] = tin[(r * LB + i) * 2 + 1]; }
+                } else {                              // padding blocks: the identity
 #pragma unroll
-                for (int m = 0; m < r; ++m) {
-                    sr = fma(cr[r][m], tr[m], fma(-ci[r][m], ti[m], sr));
-                    si = fma(cr[r][m], ti[m], fma(ci[r][m], tr[m], si));
+                    for (int r = 0; r < LB; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
                 }
-                tr[r] = (r == i) ? inv_rr : (r > i ? -sr * inv_rr : (Wt)0);
-                ti[r] = (r > i) ? -si * inv_rr : (Wt)0;
-            }
-            if (blk_bad) {
+            } else {
+                Wt cr[LB][LB], ci[LB][LB];
+#pragma unroll
+                for (int r = 0; r < LB; ++r)
+#pragma unroll
+                    for (int c = 0; c <= r; ++c) { cr[r][c] = sD[(cb + r) * LB + c]; ci[r][c] = sD[KP * LB + (cb + r) * LB + c]; }
+                Wt diag = 0;
+#pragma unroll
+                for (int r = 0; r < LB; ++r)
+                    if (r == i) diag = cr[r][r];
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    Wt d = cr[j][j];
+                    if (!(d > 0) || !__builtin_isfinite(d)) { blk_bad = true; d = 1; }
+                    const Wt l = sqrt(d), inv = (Wt)1 / l;
+                    cr[j][j] = l;
+                    ci[j][j] = inv;
+#pragma unroll
+                    for (int r = j + 1; r < LB; ++r) { cr[r][j] = cr[r][j] * inv; ci[r][j] = ci[r][j] * inv; }
+#pragma unroll
+                    for (int r = j + 1; r < LB; ++r)
+#pragma unroll
+                        for (int c = j + 1; c <= r; ++c) {
+                            cr[r][c] = fma(-cr[r][j], cr[c][j], fma(-ci[r][j], ci[c][j], cr[r][c]));
+                            ci[r][c] = fma(-ci[r][j], cr[c][j], fma(cr[r][j], ci[c][j], ci[r][c]));
+                        }
+                }
 #pragma unroll
                 for (int r = 0; r < LB; ++r) {
-                    tr[r] = 0; ti[r] = 0;
-                    if (r == i) tr[r] = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / sqrt(diag) : (Wt)1;
+                    const Wt inv_rr = ci[r][r];
+                    Wt sr = 0, si = 0;
+#pragma unroll
+                    for (int m = 0; m < r; ++m) {
+                        sr = fma(cr[r][m], tr[m], fma(-ci[r][m], ti[m], sr));
+                        si = fma(cr[r][m], ti[m], fma(ci[r][m], tr[m], si));
+                    }
+                    tr[r] = (r == i) ? inv_rr : (r > i ? -sr * inv_rr : (Wt)0);
+                    ti[r] = (r > i) ? -si * inv_rr : (Wt)0;
+                }
+                if (blk_bad) {
+#pragma unroll
+                    for (int r = 0; r < LB; ++r) {
+                        tr[r] = 0; ti[r] = 0;
+                        if (r == i) tr[r] = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / sqrt(diag) : (Wt)1;
+                    }
                 }
             }
             if (act) {
@@ -448,6 +459,11 @@ void slab_kernel(const FusedParams P) {
                     sT[KP * LB + (cb + r) * LB + i] = ti[r];
                 }
                 if (blk_bad && i == 0) myflag |= FLAG_BLOCK_NOT_PD;
+                if (P.T_out && cblk == 0 && cb < K) {  // column i of this block of T
+                    Wt* tout = static_cast<Wt*>(P.T_out) + ((size_t)ch * K + cb) * LB * 2;
+#pragma unroll
+                    for (int r = 0; r < LB; ++r) { tout[(r * LB + i) * 2] = tr[r]; tout[(r * LB + i) * 2 + 1] = ti[r]; }
+                }
             }
             if constexpr (left) {
                 __syncthreads();

@@ -56,17 +56,20 @@ def oracle_sched(name, refresh=0, refine=0, variant=0, fma=True, accum="exact"):
 
 
 def oracle_detect(wl, qam, iters, L, name, io=np.complex128, refresh=0, refine=0, variant=0, fma=True, H=None, Y=None,
-                  accum="exact"):
+                  accum="exact", T_given=None):
     Hn = (wl.H if H is None else H).astype(io).astype(np.complex128)
     Yn = (wl.Y if Y is None else Y).astype(io).astype(np.complex128)
-    return D.detect(Hn, Yn, wl.sigma2, qam, iters, L, oracle_sched(name, refresh, refine, variant, fma, accum))
+    return D.detect(Hn, Yn, wl.sigma2, qam, iters, L, oracle_sched(name, refresh, refine, variant, fma, accum),
+                    T_given=T_given)
 
 
-def oracle_spread(wl, qam, iters, L, name, io=np.complex128, refresh=0, refine=0, variant=0, H=None, Y=None):
+def oracle_spread(wl, qam, iters, L, name, io=np.complex128, refresh=0, refine=0, variant=0, H=None, Y=None,
+                  T_given=None):
     """Per-column distance between two valid rounding orders of the same
     algorithm: every sum rounded once vs the same sums as ordered FMA chains."""
-    r1 = oracle_detect(wl, qam, iters, L, name, io, refresh, refine, variant, H=H, Y=Y, accum="exact")
-    r2 = oracle_detect(wl, qam, iters, L, name, io, refresh, refine, variant, H=H, Y=Y, accum="sequential")
+    r1 = oracle_detect(wl, qam, iters, L, name, io, refresh, refine, variant, H=H, Y=Y, accum="exact", T_given=T_given)
+    r2 = oracle_detect(wl, qam, iters, L, name, io, refresh, refine, variant, H=H, Y=Y, accum="sequential",
+                       T_given=T_given)
     r1.x_alt = r2.xhat                     # the second valid order, for labels_consistent
     return np.linalg.norm(r1.xhat - r2.xhat, axis=-2), r1
 

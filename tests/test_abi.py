@@ -247,3 +247,20 @@ def test_policy_calls_validate_on_the_host(fp):
     assert L.fpcg_expected_kappa(None, None, 8, 256, 64, 14, None, None, 1, None, 4, 16, ctypes.byref(k)) == -1
     s = fp.schedule("fp8")
     assert L.fpcg_gram(None, None, 8, 64, 32, 14, None, None, 1, None, ctypes.byref(s), None, None, None) == -1
+
+
+def test_detect_pc_rejects_mode_and_block_size_before_anything_else():
+    """fpcg_detect_pc: the mode and block size are checked first (no context
+    or device needed), with FPCG_E_INVAL and a message."""
+    import ctypes
+
+    import paper_2504_09820_amd as fp
+
+    L = fp.lib()
+    args = [None, None, 4, 64, 16, 2, None, None, 1, None, 16, 4]
+    st = L.fpcg_detect_pc(*args, 4, None, None, None, None, None, 3)
+    assert st == fp.E_INVAL and b"mode" in L.fpcg_last_error()
+    st = L.fpcg_detect_pc(*args, 0, None, None, None, None, None, fp.PRECOND_STORE)
+    assert st == fp.E_INVAL and b"block_L" in L.fpcg_last_error()
+    st = L.fpcg_detect_pc(*args, 4, None, None, None, None, None, fp.PRECOND_LOAD)
+    assert st == fp.E_INVAL and b"ctx" in L.fpcg_last_error()

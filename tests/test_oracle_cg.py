@@ -562,3 +562,47 @@ def test_split_form_refinement_and_low_precision():
     r1 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 10, 4, D.schedule("fp16", variant=2, refresh_every=3))
     r0 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 10, 4, D.schedule("fp16", variant=0, refresh_every=3))
     assert np.linalg.norm(r1.xhat - xs) / np.linalg.norm(xs) < 2 * np.linalg.norm(r0.xhat - xs) / np.linalg.norm(xs) + 1e-4
+
+
+# ---------------------------------------------------------------- a kept block-Jacobi factor
+def test_given_factor_of_this_channel_reproduces_the_factorisation():
+    """T_given = the factor of this A: the symmetric form is bitwise the
+    default path (the same T), the left form equals it to FP64 rounding
+    (M_d formed as T^H T instead of C^{-H} C^{-1})."""
+    wl = small_wl(B=4, Nbs=64, K=16, R=3, zeta=0.6, seed=11)
+    A, _ = D.gram(wl.H, wl.Y, wl.sigma2)
+    T, _ = D.bj_factor(A, 4)
+    r2 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.Schedule(variant=2))
+    g2 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.Schedule(variant=2), T_given=T)
+    assert np.array_equal(r2.xhat, g2.xhat) and np.array_equal(r2.labels, g2.labels)
+    r1 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.Schedule(variant=1))
+    g1 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 6, 4, D.Schedule(variant=1), T_given=T)
+    assert np.linalg.norm(r1.xhat - g1.xhat) / np.linalg.norm(r1.xhat) < 1e-12
+
+
+def test_identity_factor_is_plain_cg_bitwise():
+    """T = I: A_bar = A exactly, b_bar = b, x = x_bar, so the symmetric form is
+    Alg. 2 on A, bit for bit."""
+    wl = small_wl(B=3, Nbs=32, K=8, R=2, zeta=0.5, seed=12)
+    eye = np.broadcast_to(np.eye(8, dtype=np.complex128), (3, 8, 8)).copy()
+    for name in ("fp64", "fp16"):
+        s0 = D.schedule(name)
+        s2 = D.schedule(name, variant=2)
+        r0 = D.detect(wl.H, wl.Y, wl.sigma2, 16, 5, 0, s0)
+        g = D.detect(wl.H, wl.Y, wl.sigma2, 16, 5, 4, s2, T_given=eye)
+        assert np.array_equal(r0.xhat, g.xhat), name
+
+
+def test_stale_factor_still_converges_to_lmmse():
+    """Any Hermitian positive definite preconditioner leaves the CG solution
+    unchanged: with the factor of an earlier, different channel realisation
+    (Gauss-Markov step), FP64 PCG at I = 3K reaches the Cholesky LMMSE solution
+    of the new channel, in both forms."""
+    wls = W.gauss_markov(3, 64, 16, 2, 16, 20.0, 0.6, 0.6, steps=2, fd_hz=1000.0, seed=13)
+    A0, _ = D.gram(wls[0].H, wls[0].Y, wls[0].sigma2)
+    T0, _ = D.bj_factor(A0, 4)
+    A1, b1 = D.gram(wls[1].H, wls[1].Y, wls[1].sigma2)
+    xs = D.lmmse(A1, b1)
+    for v in (1, 2):
+        g = D.detect(wls[1].H, wls[1].Y, wls[1].sigma2, 16, 48, 4, D.Schedule(variant=v), T_given=T0)
+        assert np.max(np.linalg.norm(g.xhat - xs, axis=-2) / np.linalg.norm(xs, axis=-2)) < 1e-10
