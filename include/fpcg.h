@@ -395,7 +395,9 @@ fpcg_status fpcg_select_precision(int32_t N, double kappa, int32_t allow_fp8,
  * slot's stream and copies the results back.  Requests that arrive while
  * others run are admitted as memory and slots free up, so their work overlaps
  * on the device.  Every channel is computed by its own workgroup in a fixed
- * order, so a request's result is bitwise the same alone and in any mix. */
+ * order, so a request's result is bitwise the same alone and in any mix.
+ * The host copies between the request's buffers and pinned staging run on
+ * the server's own worker threads; fpcg_poll only schedules. */
 typedef struct {
     int64_t B;
     int32_t Nbs, K, R;
@@ -427,6 +429,20 @@ fpcg_status fpcg_server_channels(fpcg_server* srv, int64_t B, int32_t Nbs, int32
 /* Releases a channel set once no queued or running request uses it
  * (FPCG_E_BUSY otherwise; FPCG_E_INVAL for an unknown handle). */
 fpcg_status fpcg_server_release(fpcg_server* srv, uint64_t handle);
+
+/* A resident channel set also keeps the block-Jacobi factor T of eq. pre_BJ
+ * (as fpcg_detect_pc stores it) for each (block_L, sched.gram_op,
+ * sched.work) it is served with, counted against the budget: the first
+ * request of that class on the set stores it, later ones read it in place of
+ * the block factorisation (bitwise the same results while the channels are
+ * unchanged; no factor is kept where it would not fit the budget).
+ * fpcg_server_channels_update replaces the set's H and sigma2 (same sizes,
+ * host buffers) with the channels' next realisation; with keep_precond the
+ * kept factors stay and the following requests precondition with the
+ * previous realisation's factor (Sec. V, time-varying channel), without it
+ * they are dropped.  FPCG_E_BUSY while a request uses the set. */
+fpcg_status fpcg_server_channels_update(fpcg_server* srv, uint64_t handle, const void* H, const double* sigma2,
+                                        int32_t keep_precond);
 
 /* n_slots concurrent streams (1..16), queue_cap pending requests (>= 1). */
 fpcg_status fpcg_server_create(fpcg_ctx* ctx, int32_t n_slots, int32_t queue_cap, fpcg_server** out);

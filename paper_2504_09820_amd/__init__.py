@@ -102,6 +102,8 @@ def lib():
     L.fpcg_server_channels.restype = st
     L.fpcg_server_release.argtypes = [vp, ctypes.c_uint64]
     L.fpcg_server_release.restype = st
+    L.fpcg_server_channels_update.argtypes = [vp, ctypes.c_uint64, vp, vp, i32]
+    L.fpcg_server_channels_update.restype = st
     L.fpcg_strerror.argtypes = [i32]
     L.fpcg_strerror.restype = ctypes.c_char_p
     L.fpcg_last_error.argtypes = []
@@ -515,6 +517,22 @@ class Server:
     def release(self, handle):
         _check(lib().fpcg_server_release(self._h, handle))
         self._chans.pop(handle, None)
+
+    def channels_update(self, handle, H, sigma2, keep_precond: bool = True):
+        """Replace a channel set's H and sigma2 with the channels' next
+        realisation (same shape and dtype); keep_precond keeps the block-Jacobi
+        factors the set holds, so later requests precondition with them."""
+        import numpy as np
+
+        if handle not in self._chans:
+            raise ValueError(f"unknown channel-set handle {handle}")
+        B, Nbs, K, dt = self._chans[handle]
+        H = np.ascontiguousarray(H)
+        s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
+        if H.shape != (B, Nbs, K) or H.dtype != dt or s2.shape != (B,):
+            raise ValueError(f"H must be {dt} of shape {(B, Nbs, K)} and sigma2 of shape ({B},)")
+        _check(lib().fpcg_server_channels_update(self._h, handle, H.ctypes.data, s2.ctypes.data,
+                                                 1 if keep_precond else 0))
 
     def submit(self, H, Y, sigma2, qam, iters, L=0, schedule_: "str | Schedule" = "fp64",
                refresh_every=0, refine_steps=0, variant=0, channels=None):

@@ -160,3 +160,68 @@ def test_resident_channel_sets_match_alone_bitwise():
     assert held < held_before
     srv.close()
     ctx.close()
+
+
+def test_kept_factor_across_channel_updates():
+    """A resident set keeps its block-Jacobi factor: the first request stores
+    it, the rest (several in flight at once on other slots) read it and match
+    the direct launch bitwise.  After fpcg_server_channels_update with the
+    next Gauss-Markov realisation and keep_precond, requests match a direct
+    launch of the new channels with the previous realisation's factor
+    (fpcg_detect_pc load); after an update without it, a plain launch."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    dev = torch.device("cuda:0")
+    steps = W.gauss_markov(96, 128, 32, 14, 64, 20.0, 0.6, 0.6, steps=3, fd_hz=1000.0, seed=77)
+    io = np.complex64
+    q, it, L, sched, v = 64, 11, 4, "fp16", 2
+    ctx = fp.Context(0)
+    srv = fp.Server(ctx, n_slots=4, queue_cap=64)
+    h = srv.channels(steps[0].H.astype(io), steps[0].sigma2)
+
+    def serve(Ys):
+        tickets = [srv.submit(None, Yb, None, q, it, L, sched, variant=v, channels=h) for Yb in Ys]
+        out, t0 = {}, time.time()
+        while len(out) < len(tickets):
+            for t in tickets:
+                if t not in out:
+                    r = srv.poll(t)
+                    if r is not None:
+                        out[t] = r
+            assert time.time() - t0 < 60
+        return [out[t] for t in tickets]
+
+    def direct(H, Y, s2, precond=None, mode=None):
+        x, lab, fl = fp.detect(torch.from_numpy(H).to(dev), torch.from_numpy(Y).to(dev), torch.from_numpy(s2).to(dev),
+                               q, it, L, sched, variant=v, precond=precond, precond_mode=mode)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), lab.cpu().numpy(), fl.cpu().numpy().astype(np.uint32)
+
+    def same(a, s):
+        assert np.array_equal(a[0].view(np.uint8), s[0].view(np.uint8))
+        assert np.array_equal(a[1], s[1]) and np.array_equal(a[2], s[2])
+
+    _say("case serving: kept factor, 5 blocks of received vectors per realisation, 3 realisations")
+    H0, s0 = steps[0].H.astype(io), steps[0].sigma2
+    Ys = [(steps[0].Y * (1.0 + 0.1 * k)).astype(io) for k in range(5)]
+    for Yb, s in zip(Ys, serve(Ys)):
+        same(direct(H0, Yb, s0), s)
+    # the previous realisation's factor, as a direct launch would keep it
+    T0 = torch.zeros((96, 32, L), dtype=torch.complex64, device=dev)
+    direct(H0, Ys[0], s0, T0, "store")
+    H1, s1 = steps[1].H.astype(io), steps[1].sigma2
+    srv.channels_update(h, H1, s1, keep_precond=True)
+    Ys = [(steps[1].Y * (1.0 + 0.1 * k)).astype(io) for k in range(5)]
+    for Yb, s in zip(Ys, serve(Ys)):
+        same(direct(H1, Yb, s1, T0, "load"), s)
+    H2, s2 = steps[2].H.astype(io), steps[2].sigma2
+    srv.channels_update(h, H2, s2, keep_precond=False)
+    Ys = [steps[2].Y.astype(io)]
+    same(direct(H2, Ys[0], s2), serve(Ys)[0])
+    with pytest.raises(ValueError):
+        srv.channels_update(h, H2[:5], s2[:5])
+    srv.release(h)
+    srv.close()
+    ctx.close()
