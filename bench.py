@@ -147,7 +147,7 @@ def write_traffic(args, fetch_csv, write_csv):
         cd = dict(sched=args.schedule, L=0 if args.L == "auto" else int(args.L), refresh=args.refresh,
                   refine=args.refine, variant=args.variant)
     L = cd["L"]
-    it = args.iters or FIXED_ITERS.get(args.config) or 16
+    it = args.iters if args.iters is not None else (FIXED_ITERS.get(args.config) or 16)
     rec = {"config": args.config, "schedule": cd["sched"], "L": L, "variant": cd["variant"], "iters": it,
            "refresh": cd["refresh"], "refine": cd["refine"],
            "kernel_source_hash": kernel_source_hash(),
@@ -893,7 +893,7 @@ def profile_run(args):
     if args.schedule != "auto":
         cd = dict(sched=args.schedule, L=0 if args.L == "auto" else int(args.L), refresh=args.refresh,
                   refine=args.refine, variant=args.variant)
-    it = args.iters or FIXED_ITERS.get(args.config) or 16
+    it = args.iters if args.iters is not None else (FIXED_ITERS.get(args.config) or 16)
     g = torch.Generator(device=dev)
     g.manual_seed(7)
     H = (torch.randn(B, Nbs, K, dtype=torch.complex64, device=dev, generator=g) / math.sqrt(Nbs)).contiguous()
@@ -1255,7 +1255,9 @@ def main():
                          "is timed beside them)")
     ap.add_argument("--L", default="auto", help="Jacobi block size (0 = FP-CG), or 'auto' for the faster of 4 and 8")
     ap.add_argument("--variant", type=int, default=2, help="block-Jacobi form (0 Alg. 3 as printed, 1 textbook, 2 symmetric)")
-    ap.add_argument("--iters", type=int, default=0, help="mixed-schedule iterations (0 = BER-parity search)")
+    ap.add_argument("--iters", type=int, default=None,
+                    help="mixed-schedule iterations (default: BER-parity search; with --profile the workload's "
+                         "count, 0 = the Gram, setup and slicer alone)")
     ap.add_argument("--iters64", type=int, default=0, help="FP64 iterations (0 = BER-parity search)")
     ap.add_argument("--refresh", type=int, default=0, help="FP64 refresh period (explicit --schedule only)")
     ap.add_argument("--refine", type=int, default=0, help="FP64 refinement steps (explicit --schedule only)")
