@@ -686,3 +686,71 @@ def test_slab_isolates_nonfinite_and_zero_channels():
     ref = oracle_detect(wl, 16, 8, 4, "fp16", np.complex64, variant=2, H=H, Y=Y)
     assert np.array_equal(fl, ref.flags.astype(np.int64)), (fl, ref.flags)
     assert np.all(x[1] == 0) and np.all(x[3] == 0)
+
+
+# --------------------------------------------------------------- the timed launches at full size
+# (config, schedule, L, I, refresh, variant): the slab-form launches the
+# benchmark times at c3 and c4 -- the configured FP-BJ-CG schedule, the
+# heuristic's pick and FP64 CG, at the iteration counts the BER-parity
+# search settles on
+TIMED_FULL = [
+    ("c3", "fp16", 4, 20, 4, 2),
+    ("c3", "fp32", 4, 20, 0, 2),
+    ("c3", "fp64", 0, 27, 0, 0),
+    ("c4", "fp32", 0, 130, 0, 0),
+    ("c4", "fp64", 0, 92, 0, 0),
+]
+_FULL_WL = {}
+
+
+def _full_workload(cfg):
+    if cfg not in _FULL_WL:
+        _FULL_WL.clear()                              # one full-size batch held at a time
+        c = W.CONFIGS[cfg]
+        _FULL_WL[cfg] = W.draw(c["B"], c["Nbs"], c["K"], c["R"], c["q"], c["snr_db"], c["zeta"], c["zeta"], seed=79)
+    return _FULL_WL[cfg]
+
+
+@pytest.mark.parametrize("case", TIMED_FULL, ids=[f"{c[0]}-{c[1]}-L{c[2]}-I{c[3]}" for c in TIMED_FULL])
+def test_timed_slab_launches_full_size_sampled(case):
+    """Full batch in the slab form, checked on sampled channels (the first,
+    the last and random ones) against the oracle: the spread bar of the
+    smaller cases, labels, flags, and the batch's BER against the sample's."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    cfg, sched, L, iters, refresh, variant = case
+    c = W.CONFIGS[cfg]
+    _say(f"case timed full-size {cfg} slab {sched} L={L} I={iters} refresh={refresh} B={c['B']}")
+    wl = _full_workload(cfg)
+    dev = torch.device("cuda:0")
+    io = np.complex64
+    ctx = fp.Context(0)
+    ctx.set_launch_form("slab")
+    Ht = torch.from_numpy(wl.H.astype(io)).to(dev)
+    Yt = torch.from_numpy(wl.Y.astype(io)).to(dev)
+    st = torch.from_numpy(wl.sigma2).to(dev)
+    x, lab, fl = fp.detect(Ht, Yt, st, c["q"], iters, L, sched, refresh_every=refresh, variant=variant, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+    del Ht, Yt
+    x = x.cpu().numpy().astype(np.complex128)
+    lab = lab.cpu().numpy().astype(np.int64)
+    fl = fl.cpu().numpy().astype(np.int64)
+    rng = np.random.default_rng(1)
+    n = 12 if cfg == "c3" else 6
+    idx = np.unique(np.concatenate([[0, c["B"] - 1], rng.choice(c["B"], n - 2, replace=False)]))
+    sub = W.Workload(H=wl.H[idx], Y=wl.Y[idx], labels=wl.labels[idx], X=wl.X[idx], sigma2=wl.sigma2[idx],
+                     q=c["q"], snr_db=wl.snr_db[idx])
+    spread, ref = oracle_spread(sub, c["q"], iters, L, sched, io, refresh=refresh, variant=variant)
+    _spread_parity(x[idx], ref, spread, sched, f"timed {cfg} {sched}", io)
+    ok, nc, bad = labels_consistent(lab[idx], ref.labels, x[idx], ref.xhat, c["q"], x_alt=getattr(ref, "x_alt", None))
+    assert ok, (nc, bad)
+    assert np.array_equal(fl[idx], ref.flags.astype(np.int64))
+    assert not fl.any()
+    ber = D.bit_errors(lab, wl.labels) / (lab.size * np.log2(c["q"]))
+    ber_o = D.bit_errors(ref.labels, sub.labels) / (ref.labels.size * np.log2(c["q"]))
+    nbits = ref.labels.size * np.log2(c["q"])
+    _say(f"  full-batch BER {ber:.4f} (oracle on the sample {ber_o:.4f})")
+    assert abs(ber - ber_o) <= 5 * np.sqrt(ber_o * (1 - ber_o) / nbits) + 1e-3
