@@ -1073,8 +1073,9 @@ def batch_bench(args):
     if args.schedule == "auto" and hf != "fp64" and all(cd["sched"] != hf for cd in cands):
         # the heuristic's format at the configured block size, else without a
         # preconditioner where that is the combination built
-        for L in (cands[0]["L"], 0):
-            trial = dict(cands[0], sched=hf, refresh=0, refine=0, L=L, variant=cands[0]["variant"] if L else 0)
+        # (the configured form of Alg. 3 first, then the symmetric form)
+        for L, v in ((cands[0]["L"], cands[0]["variant"]), (cands[0]["L"], 2), (0, 0)):
+            trial = dict(cands[0], sched=hf, refresh=0, refine=0, L=L, variant=v if L else 0)
             if fp.check(B, Nbs, K, R, q, 8, L, fp.schedule(hf, variant=trial["variant"])) == 0:
                 heur_cd = trial
                 break

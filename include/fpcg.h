@@ -214,11 +214,15 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  *   qam_order in {4, 16, 64, 256}; iters >= 0 (0 gives x_hat = 0).
  *   block_L = 0: Alg. 2 (no preconditioner); block_L in {4, 8, 16}: Alg. 3,
  *   block_L must divide K; each lane of the kernel owns whole Jacobi blocks,
- *   so L <= 8 below K = 65 and L = 16 runs the K <= 128 build.
+ *   so L <= 8 below K = 65 and L = 16 runs the K <= 128 build -- except FP32
+ *   operands with L = 16 in the symmetric form (variant 2), built in the
+ *   slab form at K <= 64 and K <= 128, where the blocks are the 16 x 16
+ *   diagonal tiles.
  *   65 <= K <= 128 is built for fp8, fp16 and bf16 operands, left block-Jacobi
  *   forms (variant 0 or 1) and no FP64 refresh (with fp8 also with FP64
- *   refinement), and for FP64 and FP32 operands without a preconditioner (the
- *   slab form).  Other combinations return FPCG_E_UNSUPPORTED.
+ *   refinement), for FP64 operands without a preconditioner and for FP32
+ *   operands without one or with L = 16 in the symmetric form (the slab
+ *   form).  Other combinations return FPCG_E_UNSUPPORTED.
  *   sched = NULL selects the schedule by the precision heuristic (eq.
  *   heuristic for block_L = 0, eq. heuristic_bj otherwise): with kappa the
  *   expected condition number the context holds for (Nbs, K, block_L)

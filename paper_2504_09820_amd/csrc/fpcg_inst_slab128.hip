@@ -1,6 +1,7 @@
 // Slab-kernel instantiations for K = 128 (eight waves per channel) with FP64
 // and FP32 operands: the u_W matrix does not fit LDS beside the rest, so only
-// the register-resident layout holds it.
+// the register-resident layout holds it.  FP32 also with L = 16 (symmetric
+// form).
 #include "fpcg_registry.hpp"
 
 namespace fpcg {
@@ -8,6 +9,7 @@ namespace fpcg {
 void register_slab128(std::vector<KernelEntry>& v) {
     FPCG_SLAB_IO(128, F64, 0);
     FPCG_SLAB_IO(128, F32, 0);
+    FPCG_SLAB_IO(128, F32, 16);
 }
 
 }  // namespace fpcg

@@ -11,6 +11,7 @@ void register_slab64(std::vector<KernelEntry>& v) {
     FPCG_SLAB_IO(64, BF16, 4);
     FPCG_SLAB_IO(64, F32, 0);
     FPCG_SLAB_IO(64, F32, 4);
+    FPCG_SLAB_IO(64, F32, 16);
 }
 
 }  // namespace fpcg

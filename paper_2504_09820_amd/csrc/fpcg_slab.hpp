@@ -43,7 +43,7 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
     static constexpr int KP = KP_, FMT = FMT_, LB = LB_;
     static_assert(KP == 64 || KP == 128, "slab kernel: K = 64 or 128");
     static_assert(FMT == F64 || FMT == F32 || FMT == F16 || FMT == BF16, "slab kernel: no fp8");
-    static_assert(LB == 0 || LB == 4, "slab kernel: L = 0 or 4");
+    static_assert(LB == 0 || LB == 4 || LB == 16, "slab kernel: L = 0, 4 or 16");
     static constexpr int NW = KP / 16, F = KP / 16, NT = 64 * NW;
     static constexpr bool LOWP = (FMT == F16 || FMT == BF16);
     using Wt = typename std::conditional<FMT == F64, double, float>::type;
@@ -115,6 +115,7 @@ void slab_kernel(const FusedParams P) {
     constexpr int KPLG = C::KPLG, NLD = C::NLD, KBG = C::KBG;
     constexpr bool split = (LB > 0) && SPLIT;
     constexpr bool left = (LB > 0) && !SPLIT;
+    static_assert(LB != 16 || (SPLIT && FMT != F64), "slab kernel: L = 16 in the symmetric form, u_W = fp32");
     constexpr uint32_t ES = CxB<IOT>::bytes;
     extern __shared__ __align__(16) unsigned char smem[];
 
@@ -343,6 +344,189 @@ void slab_kernel(const FusedParams P) {
     }
     __syncthreads();
 
+    // ------------------------------------------------------------ block-Jacobi setup, L = 16
+    // The Jacobi blocks are the diagonal 16 x 16 tiles.  Wave w factors tile
+    // (w, w) -- lane n owns row n, the factor's columns pass through LDS one
+    // step at a time -- and forms T_w = C_w^{-1} by forward substitution, lane
+    // n column n.  Every upper tile is then rewritten in place as
+    // T_a A_ab T_b^H, two 16 x 16 x 16 complex products on the fp32 matrix
+    // cores, before the waves read their column slabs: A_bar arrives in the
+    // layout the iteration uses.  b_bar = T_w b_w likewise.
+    if constexpr (LB == 16) {
+        using OF = Op<F32, 1>;
+        using f4 = typename OF::acc;
+        Wt* sCr = sD;                                 // C, rows 16 w + r: [K][16] re, then im
+        Wt* sCi = sD + KP * LB;
+        Wt* sTr = sT;                                 // T, the same layout
+        Wt* sTi = sT + KP * LB;
+        const int rb = 16 * wave, i = n;
+        Wt tr[16], ti[16];
+        bool blk_bad = false;
+        if (P.T_in) {                                 // a given factor replaces the factorisation
+            if (rb < K) {
+                const Wt* tin = static_cast<const Wt*>(P.T_in) + ((size_t)ch * K + rb) * LB * 2;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) { tr[r] = tin[(r * LB + i) * 2]; ti[r] = tin[(r * LB + i) * 2 + 1]; }
+            } else {                                  // padding block: the identity
+#pragma unroll
+                for (int r = 0; r < 16; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
+            }
+        } else {
+            const int qd = tile_index(wave, wave, F);
+            Wt ar[16], ai[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                ar[c] = sTile[((size_t)qd * 2 + 0) * 256 + i * 16 + c];
+                ai[c] = sTile[((size_t)qd * 2 + 1) * 256 + i * 16 + c];
+            }
+            Wt diag = 0;                              // a_ii, for the not-PD fallback
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c == i) diag = ar[c];
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (i == j) {
+                    Wt d = ar[j];
+                    if (!(d > 0) || !__builtin_isfinite(d)) { bad = true; d = 1; }
+                    const Wt l = sqrt(d);
+                    if (g == 0) { sCr[(rb + j) * LB + j] = l; sCi[(rb + j) * LB + j] = (Wt)1 / l; }
+                }
+                __syncthreads();
+                const Wt inv = sCi[(rb + j) * LB + j];
+                const Wt lr = ar[j] * inv, li = ai[j] * inv;
+                if (i > j && g == 0) { sCr[(rb + i) * LB + j] = lr; sCi[(rb + i) * LB + j] = li; }
+                __syncthreads();
+                if (i > j) {
+#pragma unroll
+                    for (int k = j + 1; k < 16; ++k) {   // a_ik -= l_ij conj(l_kj), needed for k <= i
+                        const Wt kr = sCr[(rb + k) * LB + j], ki = sCi[(rb + k) * LB + j];
+                        ar[k] = fma(-lr, kr, fma(-li, ki, ar[k]));
+                        ai[k] = fma(-li, kr, fma(lr, ki, ai[k]));
+                    }
+                }
+            }
+            blk_bad = __ballot(bad) != 0;
+            // column i of T = C^{-1}: C t = e_i by forward substitution, a
+            // column of C at a time (the imaginary diagonal slot holds 1 / c_mm)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
+            int cm = rb * LB;                         // offset of column m of C (rows rb ...)
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const Wt inv_mm = sCi[cm + m * LB + m];
+                tr[m] = tr[m] * inv_mm;
+                ti[m] = ti[m] * inv_mm;
+                // the column's loads wait for t_m: an offset that depends on it
+                // keeps them from all being issued ahead into registers
+                asm("" : "+v"(cm) : "v"(tr[m]), "v"(ti[m]));
+#pragma unroll
+                for (int r = m + 1; r < 16; ++r) {   // t_r -= c_rm t_m
+                    const Wt cr_ = sCr[cm + r * LB + m], ci_ = sCi[cm + r * LB + m];
+                    tr[r] = fma(-cr_, tr[m], fma(ci_, ti[m], tr[r]));
+                    ti[r] = fma(-cr_, ti[m], fma(-ci_, tr[m], ti[r]));
+                }
+            }
+            if (blk_bad) {
+                // not positive definite: T = diag(a_ii)^{-1/2}, so M_d = diag(a_ii)^{-1}
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    tr[r] = 0; ti[r] = 0;
+                    if (r == i) tr[r] = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / sqrt(diag) : (Wt)1;
+                }
+                myflag |= FLAG_BLOCK_NOT_PD;
+            }
+        }
+        if (g == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { sTr[(rb + r) * LB + i] = tr[r]; sTi[(rb + r) * LB + i] = ti[r]; }
+            if (P.T_out && cblk == 0 && rb < K) {     // column i of this block of T
+                Wt* tout = static_cast<Wt*>(P.T_out) + ((size_t)ch * K + rb) * LB * 2;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) { tout[(r * LB + i) * 2] = tr[r]; tout[(r * LB + i) * 2 + 1] = ti[r]; }
+            }
+        }
+        __syncthreads();                              // every block of T in LDS
+        // the tiles this wave formed in the Gram, in place
+#pragma unroll
+        for (int s = 0; s < PPW; ++s) {
+            const int q = s * NW + wave;
+            if (q < C::NTILE) {
+                int a = 0;
+#pragma unroll
+                for (int f = 1; f < F; ++f)
+                    if (q >= tile_index(f, f, F)) a = f;
+                const int b = a + (q - tile_index(a, a, F));
+                Wt* tre = sTile + ((size_t)q * 2 + 0) * 256;
+                Wt* tim = sTile + ((size_t)q * 2 + 1) * 256;
+                // X = A_ab T_b^H: operand lane (g', n') holds A_ab[n'][4 e + g'] and
+                // conj(T_b[n'][4 e + g']) for contraction step e
+                f4 Xr = f4{0, 0, 0, 0}, Xi = f4{0, 0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = 4 * e + g;
+                    const Wt a_r = tre[n * 16 + j], a_i = tim[n * 16 + j];
+                    const Wt t_r = sTr[(16 * b + n) * LB + j], t_i = sTi[(16 * b + n) * LB + j];
+                    Xr = OF::mfma(a_r, t_r, Xr);
+                    Xr = OF::mfma(a_i, t_i, Xr);
+                    Xi = OF::mfma(a_i, t_r, Xi);
+                    Xi = OF::mfma(-a_r, t_i, Xi);
+                }
+                // A_bar_ab = T_a X: X[4 g' + e][n'] is element e of the lane's own
+                // output, T_a[n'][4 g' + e] the matching operand
+                f4 Ur = f4{0, 0, 0, 0}, Ui = f4{0, 0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 4 * g + e;
+                    const Wt t_r = sTr[(16 * a + n) * LB + r], t_i = sTi[(16 * a + n) * LB + r];
+                    Ur = OF::mfma(t_r, Xr[e], Ur);
+                    Ur = OF::mfma(-t_i, Xi[e], Ur);
+                    Ui = OF::mfma(t_r, Xi[e], Ui);
+                    Ui = OF::mfma(t_i, Xr[e], Ui);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    tre[(4 * g + e) * 16 + n] = Ur[e];
+                    tim[(4 * g + e) * 16 + n] = Ui[e];
+                }
+            }
+        }
+        // b_bar = T_w b_w
+        {
+            f4 Ur = f4{0, 0, 0, 0}, Ui = f4{0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 4 * g + e;
+                const Wt t_r = sTr[(rb + n) * LB + r], t_i = sTi[(rb + n) * LB + r];
+                Ur = OF::mfma(t_r, br_[e], Ur);
+                Ur = OF::mfma(-t_i, bi_[e], Ur);
+                Ui = OF::mfma(t_r, bi_[e], Ui);
+                Ui = OF::mfma(t_i, br_[e], Ui);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { br_[e] = Ur[e]; bi_[e] = Ui[e]; }
+        }
+        __syncthreads();                              // every tile rewritten
+        // the diagonal tile of this wave exactly Hermitian: the lower triangle
+        // the conjugate of the upper one, the diagonal real
+        {
+            const int qd = tile_index(wave, wave, F);
+            Wt* tre = sTile + ((size_t)qd * 2 + 0) * 256;
+            Wt* tim = sTile + ((size_t)qd * 2 + 1) * 256;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 4 * g + e;
+                if (r > n) {
+                    tre[r * 16 + n] = tre[n * 16 + r];
+                    tim[r * 16 + n] = -tim[n * 16 + r];
+                } else if (r == n) {
+                    tim[r * 16 + n] = 0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
     // ------------------------------------------------------------ column slab of A, own slab of b
     // Acol[f][i]: A[16f + 4g + i][16 wave + n]; AcP[f][i]: the same for column
     // 16 wave + rho(n) (the FP64 operand layout, for FP64 A p and the refresh)
@@ -371,7 +555,7 @@ void slab_kernel(const FusedParams P) {
             a_at(row, NEED_STD ? cstd : cperm, Acr[f][i], Aci[f][i]);
             if constexpr (RFR && !NEED_PERM) a_at(row, cperm, Apr[f][i], Api[f][i]);
         }
-    if constexpr (LB > 0) {
+    if constexpr (LB == 4) {
         // diagonal blocks of this slab (standard columns: tile (wave, wave) in Acr / Aci
         // for the reduced formats; FP64 holds permuted columns, so read them from LDS)
 #pragma unroll
@@ -389,7 +573,7 @@ void slab_kernel(const FusedParams P) {
 
     // ------------------------------------------------------------ 2. block-Jacobi setup (L = 4)
     Wt Mr[LB ? 4 : 1][LB ? 4 : 1], Mi[LB ? 4 : 1][LB ? 4 : 1];   // this lane's block of M_d (left form)
-    if constexpr (LB > 0) {
+    if constexpr (LB == 4) {
         {
             const bool act = tid < KP;
             const int t = act ? tid : 0;
@@ -879,7 +1063,26 @@ void slab_kernel(const FusedParams P) {
     if (broken) myflag |= FLAG_BREAKDOWN;
 
     // ------------------------------------------------------------ 4. back-transform, slicer, stores
-    if constexpr (split) {                            // x = T^H x_bar (rows of block 4 wave + g)
+    if constexpr (split && LB == 16) {                // x = T_w^H x_bar on the matrix cores
+        using OF = Op<F32, 1>;
+        using f4 = typename OF::acc;
+        const Wt* sTr = sT;
+        const Wt* sTi = sT + KP * LB;
+        const int rb = 16 * wave;
+        // x[r] = sum_j conj(T_w[j][r]) x_bar[j]: operand lane (g', n') holds
+        // conj(T_w[4 g' + e][n']) for contraction element e, x_bar[4 g' + e] its own
+        f4 Ur = f4{0, 0, 0, 0}, Ui = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const Wt t_r = sTr[(rb + 4 * g + e) * LB + n], t_i = sTi[(rb + 4 * g + e) * LB + n];
+            Ur = OF::mfma(t_r, xr[e], Ur);
+            Ur = OF::mfma(t_i, xi[e], Ur);
+            Ui = OF::mfma(t_r, xi[e], Ui);
+            Ui = OF::mfma(-t_i, xr[e], Ui);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { xr[e] = Ur[e]; xi[e] = Ui[e]; }
+    } else if constexpr (split) {                     // x = T^H x_bar (rows of block 4 wave + g)
         const int rb = 16 * wave + 4 * g;
         Wt ur[4], ui[4];
 #pragma unroll

@@ -629,6 +629,12 @@ SLAB_CASES = [
     ("K128-fp64-L0", 128, 512, 14, 256, 24, 0, "fp64", np.complex128, 0, 0),
     ("K128-fp32-L0", 128, 512, 14, 256, 24, 0, "fp32", np.complex64, 0, 0),
     ("K100-N300-R17-fp64-L0", 100, 300, 17, 64, 20, 0, "fp64", np.complex128, 0, 0),
+    # L = 16: the Jacobi blocks are the 16 x 16 diagonal tiles (symmetric form, fp32)
+    ("fp32-L16-split", 64, 256, 14, 64, 16, 16, "fp32", np.complex64, 0, 2),
+    ("fp32-L16-split-refresh3", 64, 256, 14, 64, 12, 16, "fp32", np.complex64, 3, 2),
+    ("K48-N200-R9-fp32-L16-c128", 48, 200, 9, 16, 14, 16, "fp32", np.complex128, 0, 2),
+    ("K128-fp32-L16-split", 128, 512, 14, 256, 24, 16, "fp32", np.complex64, 0, 2),
+    ("K112-N300-R17-fp32-L16", 112, 300, 17, 64, 20, 16, "fp32", np.complex64, 0, 2),
 ]
 
 
@@ -663,6 +669,50 @@ def test_slab_form_matches_oracle(case):
     ok, n, bad = labels_consistent(lab, ref.labels, x, ref.xhat, q, x_alt=getattr(ref, "x_alt", None))
     assert ok, (n, bad)
     assert np.array_equal(fl, ref.flags.astype(np.int64))
+
+
+@pytest.mark.parametrize("K,Nbs", [(64, 256), (128, 512), (80, 200)])
+def test_slab_fp32_l16_converged_within_1e5_of_lmmse(K, Nbs):
+    """FP-BJ-CG with 16 x 16 blocks and FP32 work run to convergence (I = K/2
+    here): within 1e-5 of the exact LMMSE solution (every HPD preconditioner
+    leaves the solution unchanged), labels identical away from the
+    boundaries, flags as the oracle's (none yet: run on past convergence,
+    the FP32 recurrences end in the breakdown guard, in the oracle too)."""
+    _say(f"case slab fp32 L=16 converged K={K}")
+    wl = _wl(4, Nbs, K, 14, 64, 20.0, 0.5, 66)
+    x, lab, fl = _slab_run(wl, 64, K // 2, 16, "fp32", np.complex64, 0, 2)
+    ref = oracle_detect(wl, 64, K // 2, 16, "fp32", np.complex64, variant=2)
+    A, b = D.gram(wl.H.astype(np.complex64).astype(np.complex128), wl.Y.astype(np.complex64).astype(np.complex128),
+                  wl.sigma2)
+    xs = D.lmmse(A, b)
+    e = col_rel(x, xs)
+    _say(f"  max rel error vs LMMSE {e.max():.2e}")
+    assert e.max() < 1e-5
+    far = boundary_distance(xs, 64) > 1e-3
+    assert np.array_equal(lab[far], D.slice_qam(xs, 64)[far])
+    assert np.array_equal(fl, ref.flags.astype(np.int64))
+
+
+def test_slab_l16_not_pd_block_flagged_and_isolated():
+    """A channel whose Jacobi block is singular (sigma^2 = 0 and a user's
+    column of H zero) falls back to the diagonal for that block and raises
+    BLOCK_NOT_PD, as the oracle does; the other channels are unaffected."""
+    _say("case slab L=16 not-PD block")
+    wl = _wl(5, 256, 64, 5, 16, 15.0, 0.3, 67)
+    H = wl.H.copy()
+    H[2, :, 20] = 0
+    s2 = wl.sigma2.copy()
+    s2[2] = 0.0
+    sub = W.Workload(H=H, Y=wl.Y, labels=wl.labels, X=wl.X, sigma2=s2, q=16, snr_db=wl.snr_db)
+    x, lab, fl = _slab_run(sub, 16, 8, 16, "fp32", np.complex64, 0, 2)
+    spread, ref = oracle_spread(sub, 16, 8, 16, "fp32", np.complex64, variant=2)
+    assert np.array_equal(fl, ref.flags.astype(np.int64)), (fl, ref.flags)
+    assert fl[2] != 0 and not np.delete(fl, 2).any()
+    keep = np.array([0, 1, 3, 4])
+    sp2, ref2 = oracle_spread(W.Workload(H=wl.H[keep], Y=wl.Y[keep], labels=wl.labels[keep], X=wl.X[keep],
+                                         sigma2=wl.sigma2[keep], q=16, snr_db=wl.snr_db[keep]),
+                              16, 8, 16, "fp32", np.complex64, variant=2)
+    _spread_parity(x[keep], ref2, sp2, "fp32", "not-PD neighbours", np.complex64)
 
 
 @pytest.mark.parametrize("K,Nbs,L", [(64, 256, 0), (64, 256, 4), (128, 512, 0)])
