@@ -801,9 +801,19 @@ void slab_kernel(const FusedParams P) {
             afr[c][1] = (frag)Aci[c / 4][c % 4];
         }
     }
+    // Im(W) takes -Ai pr: a negated copy of the imaginary operand, so that no
+    // sign is flipped per iteration (the products are the same)
+    frag afn[FMT == F64 ? 1 : NCH];
+    if constexpr (FMT != F64) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if constexpr (C::LOWP) afn[c] = O::neg(afr[c][1]);
+            else afn[c] = -afr[c][1];
+        }
+    }
 
     // ------------------------------------------------------------ 3. (P)CG
-    unsigned char* sPB = smain;                                        // p exchange [2][F][2][4][64]
+    unsigned char* sPB = smain;          // p exchange: [2][F][2][4][64] (u_W), [2][F/2][2][64][8 halves] (reduced)
     Wt* sXB = reinterpret_cast<Wt*>(smain + C::sz_pb);                // x exchange [F][2][4][64]
     auto pb_at = [&](int par, int s, int pl, int e, int ln) -> size_t {
         return ((((size_t)par * F + s) * 2 + pl) * 4 + e) * 64 + ln;
@@ -812,8 +822,9 @@ void slab_kernel(const FusedParams P) {
     auto publish_p = [&](int par, const Wt* pr, const Wt* pi) {
         if constexpr (C::LOWP) {
             uint32_t* d = reinterpret_cast<uint32_t*>(sPB);
-            // four halves of a plane as two words: [par][slab][plane][lane] x 2 words
-            const size_t o = (((size_t)par * F + wave) * 2) * 64 * 2;
+            // four halves of a plane as two words, beside those of the other
+            // slab of the same contraction chunk: [par][chunk][plane][lane][slab & 1][2 words]
+            const size_t o = (((size_t)par * NCH + (wave >> 1)) * 2) * 64 * 4 + (wave & 1) * 2;
             uint32_t w0, w1, v0, v1;
             if constexpr (FMT == F16) {
                 w0 = f16x2_bits(pr[0], pr[1]); w1 = f16x2_bits(pr[2], pr[3]);
@@ -822,8 +833,8 @@ void slab_kernel(const FusedParams P) {
                 w0 = bf16x2_bits(pr[0], pr[1]); w1 = bf16x2_bits(pr[2], pr[3]);
                 v0 = bf16x2_bits(pi[0], pi[1]); v1 = bf16x2_bits(pi[2], pi[3]);
             }
-            *reinterpret_cast<u32x2*>(d + o + (size_t)lane * 2) = u32x2{w0, w1};
-            *reinterpret_cast<u32x2*>(d + o + 128 + (size_t)lane * 2) = u32x2{v0, v1};
+            *reinterpret_cast<u32x2*>(d + o + (size_t)lane * 4) = u32x2{w0, w1};
+            *reinterpret_cast<u32x2*>(d + o + 256 + (size_t)lane * 4) = u32x2{v0, v1};
         } else {
             Wt* d = reinterpret_cast<Wt*>(sPB);
 #pragma unroll
@@ -836,20 +847,14 @@ void slab_kernel(const FusedParams P) {
     // B operand of chunk c, plane pl, from parity par
     auto b_op = [&](int par, int c, int pl) -> frag {
         if constexpr (C::LOWP) {
-            const uint32_t* d = reinterpret_cast<const uint32_t*>(sPB);
-            const size_t o0 = ((((size_t)par * F + 2 * c) * 2 + pl) * 64 + lane) * 2;
-            const size_t o1 = ((((size_t)par * F + 2 * c + 1) * 2 + pl) * 64 + lane) * 2;
-            const u32x2 a = *reinterpret_cast<const u32x2*>(d + o0);
-            const u32x2 b = *reinterpret_cast<const u32x2*>(d + o1);
-            return frag{a[0], a[1], b[0], b[1]};
+            // the parity's part of the offset once, the chunk's and plane's
+            // parts as constants
+            const uint32_t* d = reinterpret_cast<const uint32_t*>(sPB) + (size_t)par * NCH * 2 * 64 * 4 + lane * 4;
+            return *reinterpret_cast<const frag*>(d + (size_t)(c * 2 + pl) * 64 * 4);
         } else {
             const Wt* d = reinterpret_cast<const Wt*>(sPB);
             return (frag)d[pb_at(par, c / 4, pl, c % 4, lane)];
         }
-    };
-    auto neg_op = [&](frag v) -> frag {
-        if constexpr (C::LOWP) return O::neg(v);
-        else return -v;
     };
     // sums of a per-lane value over the column (lane groups, then waves in
     // order), two values at once; slot k of parity par
@@ -939,7 +944,7 @@ void slab_kernel(const FusedParams P) {
                 Wr = O::mfma(afr[c][0], b_r, Wr);
                 Wr = O::mfma(afr[c][1], b_i, Wr);
                 Wi = O::mfma(afr[c][0], b_i, Wi);
-                Wi = O::mfma(afr[c][1], neg_op(b_r), Wi);
+                Wi = O::mfma(afn[c], b_r, Wi);
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e) { wr[e] = (Wt)Wr[e]; wi[e] = (Wt)Wi[e]; }
