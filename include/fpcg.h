@@ -217,7 +217,8 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  *   so L <= 8 below K = 65 and L = 16 runs the K <= 128 build -- except FP32
  *   operands with L = 16 in the symmetric form (variant 2), built in the
  *   slab form at K <= 64 and K <= 128, where the blocks are the 16 x 16
- *   diagonal tiles.
+ *   diagonal tiles.  The slab form at K <= 64 also builds L = 8 in the
+ *   symmetric form for fp16, bf16 and FP32 operands (two blocks per tile).
  *   65 <= K <= 128 is built for fp8, fp16 and bf16 operands, left block-Jacobi
  *   forms (variant 0 or 1) and no FP64 refresh (with fp8 also with FP64
  *   refinement), for FP64 operands without a preconditioner and for FP32

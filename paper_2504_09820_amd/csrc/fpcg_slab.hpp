@@ -43,7 +43,7 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
     static constexpr int KP = KP_, FMT = FMT_, LB = LB_;
     static_assert(KP == 64 || KP == 128, "slab kernel: K = 64 or 128");
     static_assert(FMT == F64 || FMT == F32 || FMT == F16 || FMT == BF16, "slab kernel: no fp8");
-    static_assert(LB == 0 || LB == 4 || LB == 16, "slab kernel: L = 0, 4 or 16");
+    static_assert(LB == 0 || LB == 4 || LB == 8 || LB == 16, "slab kernel: L = 0, 4, 8 or 16");
     static constexpr int NW = KP / 16, F = KP / 16, NT = 64 * NW;
     static constexpr bool LOWP = (FMT == F16 || FMT == BF16);
     using Wt = typename std::conditional<FMT == F64, double, float>::type;
@@ -80,8 +80,10 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
         size_t a = sz_tiles > sz_hstage ? sz_tiles : sz_hstage, b = sz_pb + (refresh ? sz_xb : 0), c = sz_stage(es);
         return a > b ? (a > c ? a : c) : (b > c ? b : c);
     }
-    static constexpr size_t sz_d = LB ? 2 * W * KP * LB : 0;
-    static constexpr size_t sz_t = LB ? 2 * W * KP * LB : 0;
+    // L = 8 and 16 keep C and T as 16-wide tiles (block diagonal for L = 8)
+    static constexpr int TS = LB >= 8 ? 16 : LB;
+    static constexpr size_t sz_d = LB ? 2 * W * KP * TS : 0;
+    static constexpr size_t sz_t = LB ? 2 * W * KP * TS : 0;
     static constexpr size_t sz_red = 2 * 2 * (size_t)NW * 16 * W;      // [parity][value][wave][column]
     __host__ __device__ static constexpr size_t lds(size_t es, bool split, bool refresh) {
         return sz_main(es, refresh) + sz_d + (split ? 1 : 2) * sz_t + sz_red;
@@ -115,7 +117,7 @@ void slab_kernel(const FusedParams P) {
     constexpr int KPLG = C::KPLG, NLD = C::NLD, KBG = C::KBG;
     constexpr bool split = (LB > 0) && SPLIT;
     constexpr bool left = (LB > 0) && !SPLIT;
-    static_assert(LB != 16 || (SPLIT && FMT != F64), "slab kernel: L = 16 in the symmetric form, u_W = fp32");
+    static_assert(LB < 8 || (SPLIT && FMT != F64), "slab kernel: L = 8 and 16 in the symmetric form, u_W = fp32");
     constexpr uint32_t ES = CxB<IOT>::bytes;
     extern __shared__ __align__(16) unsigned char smem[];
 
@@ -139,7 +141,7 @@ void slab_kernel(const FusedParams P) {
     const size_t main_bytes = C::sz_main(ES, refresh);
     Wt* sD = reinterpret_cast<Wt*>(smem + main_bytes);                 // [K][L] re, then im
     Wt* sT = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d);       // T blocks [K][L] re, im
-    Wt* sM = sT + 2 * KP * (LB ? LB : 1);                                // left form: M_d blocks
+    Wt* sM = sT + 2 * KP * (LB ? C::TS : 1);                             // left form: M_d blocks
     Wt* sRed = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d + (split ? 1 : 2) * C::sz_t);
     __shared__ uint32_t sFlag;
     if (tid == 0) sFlag = 0u;
@@ -344,85 +346,93 @@ void slab_kernel(const FusedParams P) {
     }
     __syncthreads();
 
-    // ------------------------------------------------------------ block-Jacobi setup, L = 16
-    // The Jacobi blocks are the diagonal 16 x 16 tiles.  Wave w factors tile
-    // (w, w) -- lane n owns row n, the factor's columns pass through LDS one
-    // step at a time -- and forms T_w = C_w^{-1} by forward substitution, lane
-    // n column n.  Every upper tile is then rewritten in place as
-    // T_a A_ab T_b^H, two 16 x 16 x 16 complex products on the fp32 matrix
-    // cores, before the waves read their column slabs: A_bar arrives in the
-    // layout the iteration uses.  b_bar = T_w b_w likewise.
-    if constexpr (LB == 16) {
+    // ------------------------------------------------------------ block-Jacobi setup, L = 8 and 16
+    // The Jacobi blocks tile the diagonal 16 x 16 tiles (one block of 16, or
+    // two of 8).  Wave w factors the blocks of tile (w, w) -- lane n owns row
+    // n % L of block n / L, the factor's columns pass through LDS one step at
+    // a time -- and forms their T = C^{-1} by forward substitution, lane n
+    // column n % L; T_w, the 16 x 16 block-diagonal tile of T, goes to LDS.
+    // Every upper tile is then rewritten in place as T_a A_ab T_b^H, two
+    // 16 x 16 x 16 complex products on the fp32 matrix cores, before the
+    // waves read their column slabs: A_bar arrives in the layout the
+    // iteration uses.  b_bar = T_w b_w likewise.
+    if constexpr (LB == 8 || LB == 16) {
         using OF = Op<F32, 1>;
         using f4 = typename OF::acc;
-        Wt* sCr = sD;                                 // C, rows 16 w + r: [K][16] re, then im
-        Wt* sCi = sD + KP * LB;
+        constexpr int TS = 16;                        // row stride of C and T in LDS (a tile's width)
+        Wt* sCr = sD;                                 // C, rows 16 w + r: [KP][16] re, then im
+        Wt* sCi = sD + KP * TS;
         Wt* sTr = sT;                                 // T, the same layout
-        Wt* sTi = sT + KP * LB;
-        const int rb = 16 * wave, i = n;
-        Wt tr[16], ti[16];
+        Wt* sTi = sT + KP * TS;
+        const int rb = 16 * wave;                     // first row of the tile
+        const int kb = n / LB, i = n % LB;            // block in the tile, row / column in the block
+        const int bb = rb + kb * LB;                  // first row of the block
+        const int o0 = kb * LB;                       // first column of the block in the tile
+        Wt tr[LB], ti[LB];
         bool blk_bad = false;
         if (P.T_in) {                                 // a given factor replaces the factorisation
-            if (rb < K) {
-                const Wt* tin = static_cast<const Wt*>(P.T_in) + ((size_t)ch * K + rb) * LB * 2;
+            if (bb < K) {
+                const Wt* tin = static_cast<const Wt*>(P.T_in) + ((size_t)ch * K + bb) * LB * 2;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) { tr[r] = tin[(r * LB + i) * 2]; ti[r] = tin[(r * LB + i) * 2 + 1]; }
+                for (int r = 0; r < LB; ++r) { tr[r] = tin[(r * LB + i) * 2]; ti[r] = tin[(r * LB + i) * 2 + 1]; }
             } else {                                  // padding block: the identity
 #pragma unroll
-                for (int r = 0; r < 16; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
+                for (int r = 0; r < LB; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
             }
         } else {
             const int qd = tile_index(wave, wave, F);
-            Wt ar[16], ai[16];
+            Wt ar[LB], ai[LB];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                ar[c] = sTile[((size_t)qd * 2 + 0) * 256 + i * 16 + c];
-                ai[c] = sTile[((size_t)qd * 2 + 1) * 256 + i * 16 + c];
+            for (int c = 0; c < LB; ++c) {
+                ar[c] = sTile[((size_t)qd * 2 + 0) * 256 + n * 16 + o0 + c];
+                ai[c] = sTile[((size_t)qd * 2 + 1) * 256 + n * 16 + o0 + c];
             }
             Wt diag = 0;                              // a_ii, for the not-PD fallback
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
+            for (int c = 0; c < LB; ++c)
                 if (c == i) diag = ar[c];
             bool bad = false;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < LB; ++j) {
                 if (i == j) {
                     Wt d = ar[j];
                     if (!(d > 0) || !__builtin_isfinite(d)) { bad = true; d = 1; }
                     const Wt l = sqrt(d);
-                    if (g == 0) { sCr[(rb + j) * LB + j] = l; sCi[(rb + j) * LB + j] = (Wt)1 / l; }
+                    if (g == 0) { sCr[(bb + j) * TS + o0 + j] = l; sCi[(bb + j) * TS + o0 + j] = (Wt)1 / l; }
                 }
                 __syncthreads();
-                const Wt inv = sCi[(rb + j) * LB + j];
+                const Wt inv = sCi[(bb + j) * TS + o0 + j];
                 const Wt lr = ar[j] * inv, li = ai[j] * inv;
-                if (i > j && g == 0) { sCr[(rb + i) * LB + j] = lr; sCi[(rb + i) * LB + j] = li; }
+                if (i > j && g == 0) { sCr[(bb + i) * TS + o0 + j] = lr; sCi[(bb + i) * TS + o0 + j] = li; }
                 __syncthreads();
                 if (i > j) {
 #pragma unroll
-                    for (int k = j + 1; k < 16; ++k) {   // a_ik -= l_ij conj(l_kj), needed for k <= i
-                        const Wt kr = sCr[(rb + k) * LB + j], ki = sCi[(rb + k) * LB + j];
+                    for (int k = j + 1; k < LB; ++k) {   // a_ik -= l_ij conj(l_kj), needed for k <= i
+                        const Wt kr = sCr[(bb + k) * TS + o0 + j], ki = sCi[(bb + k) * TS + o0 + j];
                         ar[k] = fma(-lr, kr, fma(-li, ki, ar[k]));
                         ai[k] = fma(-li, kr, fma(lr, ki, ai[k]));
                     }
                 }
             }
-            blk_bad = __ballot(bad) != 0;
+            // the lanes of one block: lane groups x the block's 16 / (16 / L) lanes
+            const uint64_t grp = (LB == 16) ? ~0ull : 0x00FF00FF00FF00FFull << (kb * LB);
+            blk_bad = (__ballot(bad) & grp) != 0;
             // column i of T = C^{-1}: C t = e_i by forward substitution, a
             // column of C at a time (the imaginary diagonal slot holds 1 / c_mm)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
-            int cm = rb * LB;                         // offset of column m of C (rows rb ...)
+            for (int r = 0; r < LB; ++r) { tr[r] = r == i ? (Wt)1 : (Wt)0; ti[r] = 0; }
+            int cm = bb * TS + o0;                    // offset of the block's C
 #pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const Wt inv_mm = sCi[cm + m * LB + m];
+            for (int m = 0; m < LB; ++m) {
+                const Wt inv_mm = sCi[cm + m * TS + m];
                 tr[m] = tr[m] * inv_mm;
                 ti[m] = ti[m] * inv_mm;
                 // the column's loads wait for t_m: an offset that depends on it
                 // keeps them from all being issued ahead into registers
                 asm("" : "+v"(cm) : "v"(tr[m]), "v"(ti[m]));
 #pragma unroll
-                for (int r = m + 1; r < 16; ++r) {   // t_r -= c_rm t_m
-                    const Wt cr_ = sCr[cm + r * LB + m], ci_ = sCi[cm + r * LB + m];
+                for (int r = m + 1; r < LB; ++r) {   // t_r -= c_rm t_m
+                    const Wt cr_ = sCr[cm + r * TS + m], ci_ = sCi[cm + r * TS + m];
                     tr[r] = fma(-cr_, tr[m], fma(ci_, ti[m], tr[r]));
                     ti[r] = fma(-cr_, ti[m], fma(-ci_, tr[m], ti[r]));
                 }
@@ -430,7 +440,7 @@ void slab_kernel(const FusedParams P) {
             if (blk_bad) {
                 // not positive definite: T = diag(a_ii)^{-1/2}, so M_d = diag(a_ii)^{-1}
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
+                for (int r = 0; r < LB; ++r) {
                     tr[r] = 0; ti[r] = 0;
                     if (r == i) tr[r] = (diag > 0 && __builtin_isfinite(diag)) ? (Wt)1 / sqrt(diag) : (Wt)1;
                 }
@@ -438,12 +448,21 @@ void slab_kernel(const FusedParams P) {
             }
         }
         if (g == 0) {
+            // column n of the tile of T: the block's column, zeros beside it
 #pragma unroll
-            for (int r = 0; r < 16; ++r) { sTr[(rb + r) * LB + i] = tr[r]; sTi[(rb + r) * LB + i] = ti[r]; }
-            if (P.T_out && cblk == 0 && rb < K) {     // column i of this block of T
-                Wt* tout = static_cast<Wt*>(P.T_out) + ((size_t)ch * K + rb) * LB * 2;
+            for (int r = 0; r < LB; ++r) { sTr[(bb + r) * TS + n] = tr[r]; sTi[(bb + r) * TS + n] = ti[r]; }
+            if constexpr (LB < 16) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) { tout[(r * LB + i) * 2] = tr[r]; tout[(r * LB + i) * 2 + 1] = ti[r]; }
+                for (int r = 0; r < LB; ++r) {
+                    const int orow = rb + (kb ^ 1) * LB + r;
+                    sTr[orow * TS + n] = 0;
+                    sTi[orow * TS + n] = 0;
+                }
+            }
+            if (P.T_out && cblk == 0 && bb < K) {     // column i of this block of T
+                Wt* tout = static_cast<Wt*>(P.T_out) + ((size_t)ch * K + bb) * LB * 2;
+#pragma unroll
+                for (int r = 0; r < LB; ++r) { tout[(r * LB + i) * 2] = tr[r]; tout[(r * LB + i) * 2 + 1] = ti[r]; }
             }
         }
         __syncthreads();                              // every block of T in LDS
@@ -466,7 +485,7 @@ void slab_kernel(const FusedParams P) {
                 for (int e = 0; e < 4; ++e) {
                     const int j = 4 * e + g;
                     const Wt a_r = tre[n * 16 + j], a_i = tim[n * 16 + j];
-                    const Wt t_r = sTr[(16 * b + n) * LB + j], t_i = sTi[(16 * b + n) * LB + j];
+                    const Wt t_r = sTr[(16 * b + n) * TS + j], t_i = sTi[(16 * b + n) * TS + j];
                     Xr = OF::mfma(a_r, t_r, Xr);
                     Xr = OF::mfma(a_i, t_i, Xr);
                     Xi = OF::mfma(a_i, t_r, Xi);
@@ -478,7 +497,7 @@ void slab_kernel(const FusedParams P) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int r = 4 * g + e;
-                    const Wt t_r = sTr[(16 * a + n) * LB + r], t_i = sTi[(16 * a + n) * LB + r];
+                    const Wt t_r = sTr[(16 * a + n) * TS + r], t_i = sTi[(16 * a + n) * TS + r];
                     Ur = OF::mfma(t_r, Xr[e], Ur);
                     Ur = OF::mfma(-t_i, Xi[e], Ur);
                     Ui = OF::mfma(t_r, Xi[e], Ui);
@@ -497,7 +516,7 @@ void slab_kernel(const FusedParams P) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int r = 4 * g + e;
-                const Wt t_r = sTr[(rb + n) * LB + r], t_i = sTi[(rb + n) * LB + r];
+                const Wt t_r = sTr[(rb + n) * TS + r], t_i = sTi[(rb + n) * TS + r];
                 Ur = OF::mfma(t_r, br_[e], Ur);
                 Ur = OF::mfma(-t_i, bi_[e], Ur);
                 Ui = OF::mfma(t_r, bi_[e], Ui);
@@ -1068,18 +1087,19 @@ void slab_kernel(const FusedParams P) {
     if (broken) myflag |= FLAG_BREAKDOWN;
 
     // ------------------------------------------------------------ 4. back-transform, slicer, stores
-    if constexpr (split && LB == 16) {                // x = T_w^H x_bar on the matrix cores
+    if constexpr (split && (LB == 8 || LB == 16)) {   // x = T_w^H x_bar on the matrix cores
         using OF = Op<F32, 1>;
         using f4 = typename OF::acc;
+        constexpr int TS = 16;
         const Wt* sTr = sT;
-        const Wt* sTi = sT + KP * LB;
+        const Wt* sTi = sT + KP * TS;
         const int rb = 16 * wave;
         // x[r] = sum_j conj(T_w[j][r]) x_bar[j]: operand lane (g', n') holds
         // conj(T_w[4 g' + e][n']) for contraction element e, x_bar[4 g' + e] its own
         f4 Ur = f4{0, 0, 0, 0}, Ui = f4{0, 0, 0, 0};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const Wt t_r = sTr[(rb + 4 * g + e) * LB + n], t_i = sTi[(rb + 4 * g + e) * LB + n];
+            const Wt t_r = sTr[(rb + 4 * g + e) * TS + n], t_i = sTi[(rb + 4 * g + e) * TS + n];
             Ur = OF::mfma(t_r, xr[e], Ur);
             Ur = OF::mfma(t_i, xi[e], Ur);
             Ui = OF::mfma(t_r, xi[e], Ui);

@@ -629,6 +629,11 @@ SLAB_CASES = [
     ("K128-fp64-L0", 128, 512, 14, 256, 24, 0, "fp64", np.complex128, 0, 0),
     ("K128-fp32-L0", 128, 512, 14, 256, 24, 0, "fp32", np.complex64, 0, 0),
     ("K100-N300-R17-fp64-L0", 100, 300, 17, 64, 20, 0, "fp64", np.complex128, 0, 0),
+    # L = 8: two Jacobi blocks in each diagonal tile (symmetric form)
+    ("fp16-L8-split-refresh4", 64, 256, 14, 64, 16, 8, "fp16", np.complex64, 4, 2),
+    ("fp32-L8-split", 64, 256, 14, 64, 16, 8, "fp32", np.complex64, 0, 2),
+    ("bf16-L8-split-c128", 64, 256, 14, 64, 14, 8, "bf16", np.complex128, 0, 2),
+    ("K56-N200-R20-fp16-L8-split", 56, 200, 20, 16, 14, 8, "fp16", np.complex64, 0, 2),
     # L = 16: the Jacobi blocks are the 16 x 16 diagonal tiles (symmetric form, fp32)
     ("fp32-L16-split", 64, 256, 14, 64, 16, 16, "fp32", np.complex64, 0, 2),
     ("fp32-L16-split-refresh3", 64, 256, 14, 64, 12, 16, "fp32", np.complex64, 3, 2),
@@ -671,17 +676,18 @@ def test_slab_form_matches_oracle(case):
     assert np.array_equal(fl, ref.flags.astype(np.int64))
 
 
-@pytest.mark.parametrize("K,Nbs", [(64, 256), (128, 512), (80, 200)])
-def test_slab_fp32_l16_converged_within_1e5_of_lmmse(K, Nbs):
-    """FP-BJ-CG with 16 x 16 blocks and FP32 work run to convergence (I = K/2
-    here): within 1e-5 of the exact LMMSE solution (every HPD preconditioner
-    leaves the solution unchanged), labels identical away from the
-    boundaries, flags as the oracle's (none yet: run on past convergence,
-    the FP32 recurrences end in the breakdown guard, in the oracle too)."""
-    _say(f"case slab fp32 L=16 converged K={K}")
+@pytest.mark.parametrize("K,Nbs,L", [(64, 256, 16), (128, 512, 16), (80, 200, 16), (64, 256, 8)])
+def test_slab_fp32_l16_converged_within_1e5_of_lmmse(K, Nbs, L):
+    """FP-BJ-CG with 16 x 16 (and 8 x 8) blocks and FP32 work run to
+    convergence (I = K/2 here): within 1e-5 of the exact LMMSE solution
+    (every HPD preconditioner leaves the solution unchanged), labels
+    identical away from the boundaries, flags as the oracle's (none yet: run
+    on past convergence, the FP32 recurrences end in the breakdown guard, in
+    the oracle too)."""
+    _say(f"case slab fp32 L={L} converged K={K}")
     wl = _wl(4, Nbs, K, 14, 64, 20.0, 0.5, 66)
-    x, lab, fl = _slab_run(wl, 64, K // 2, 16, "fp32", np.complex64, 0, 2)
-    ref = oracle_detect(wl, 64, K // 2, 16, "fp32", np.complex64, variant=2)
+    x, lab, fl = _slab_run(wl, 64, K // 2, L, "fp32", np.complex64, 0, 2)
+    ref = oracle_detect(wl, 64, K // 2, L, "fp32", np.complex64, variant=2)
     A, b = D.gram(wl.H.astype(np.complex64).astype(np.complex128), wl.Y.astype(np.complex64).astype(np.complex128),
                   wl.sigma2)
     xs = D.lmmse(A, b)
@@ -693,26 +699,27 @@ def test_slab_fp32_l16_converged_within_1e5_of_lmmse(K, Nbs):
     assert np.array_equal(fl, ref.flags.astype(np.int64))
 
 
-def test_slab_l16_not_pd_block_flagged_and_isolated():
+@pytest.mark.parametrize("L,sched", [(16, "fp32"), (8, "fp32"), (8, "fp16")])
+def test_slab_l16_not_pd_block_flagged_and_isolated(L, sched):
     """A channel whose Jacobi block is singular (sigma^2 = 0 and a user's
     column of H zero) falls back to the diagonal for that block and raises
     BLOCK_NOT_PD, as the oracle does; the other channels are unaffected."""
-    _say("case slab L=16 not-PD block")
+    _say(f"case slab L={L} {sched} not-PD block")
     wl = _wl(5, 256, 64, 5, 16, 15.0, 0.3, 67)
     H = wl.H.copy()
     H[2, :, 20] = 0
     s2 = wl.sigma2.copy()
     s2[2] = 0.0
     sub = W.Workload(H=H, Y=wl.Y, labels=wl.labels, X=wl.X, sigma2=s2, q=16, snr_db=wl.snr_db)
-    x, lab, fl = _slab_run(sub, 16, 8, 16, "fp32", np.complex64, 0, 2)
-    spread, ref = oracle_spread(sub, 16, 8, 16, "fp32", np.complex64, variant=2)
+    x, lab, fl = _slab_run(sub, 16, 8, L, sched, np.complex64, 0, 2)
+    spread, ref = oracle_spread(sub, 16, 8, L, sched, np.complex64, variant=2)
     assert np.array_equal(fl, ref.flags.astype(np.int64)), (fl, ref.flags)
     assert fl[2] != 0 and not np.delete(fl, 2).any()
     keep = np.array([0, 1, 3, 4])
     sp2, ref2 = oracle_spread(W.Workload(H=wl.H[keep], Y=wl.Y[keep], labels=wl.labels[keep], X=wl.X[keep],
                                          sigma2=wl.sigma2[keep], q=16, snr_db=wl.snr_db[keep]),
-                              16, 8, 16, "fp32", np.complex64, variant=2)
-    _spread_parity(x[keep], ref2, sp2, "fp32", "not-PD neighbours", np.complex64)
+                              16, 8, L, sched, np.complex64, variant=2)
+    _spread_parity(x[keep], ref2, sp2, sched, "not-PD neighbours", np.complex64)
 
 
 @pytest.mark.parametrize("K,Nbs,L", [(64, 256, 0), (64, 256, 4), (128, 512, 0)])

@@ -52,6 +52,8 @@ ROUND_TRIP = [
     ("slab", "fp64", 64, 256, 14, 4, 2, np.complex128),
     ("slab", "bf16", 64, 256, 20, 4, 1, np.complex64),
     ("slab", "fp32", 64, 256, 14, 16, 2, np.complex64),
+    ("slab", "fp16", 64, 256, 14, 8, 2, np.complex64),
+    ("slab", "fp32", 56, 200, 20, 8, 2, np.complex128),
     ("slab", "fp32", 128, 512, 14, 16, 2, np.complex128),
 ]
 
@@ -86,6 +88,7 @@ def test_store_then_load_is_bitwise_the_plain_launch(case):
 @pytest.mark.parametrize("sched,K,Nbs,L,io", [("fp64", 32, 128, 4, np.complex128), ("fp64", 64, 256, 8, np.complex128),
                                               ("fp16", 64, 256, 4, np.complex64), ("fp32", 32, 100, 8, np.complex64),
                                               ("fp32", 64, 256, 16, np.complex64),
+                                              ("fp16", 64, 256, 8, np.complex64),
                                               ("fp32", 128, 512, 16, np.complex64)])
 def test_stored_factor_matches_the_oracles(sched, K, Nbs, L, io):
     """T = C^{-1} of each diagonal block of the u_W Gram (eq. pre_BJ).  FP64:
@@ -103,7 +106,7 @@ def test_stored_factor_matches_the_oracles(sched, K, Nbs, L, io):
     tdt = torch.complex128 if sched == "fp64" else torch.complex64
     T = torch.zeros((9, K, L), dtype=tdt, device=H.device)
     for form in ("fused", "slab"):
-        if form == "slab" and not ((K == 64 and L == 4) or L == 16):
+        if form == "slab" and not ((K == 64 and L in (4, 8)) or L == 16):
             continue
         if form == "fused" and L == 16:               # L = 16 in fp32 is built as the slab form only
             continue
@@ -132,6 +135,7 @@ def test_stored_factor_matches_the_oracles(sched, K, Nbs, L, io):
     ("fp16", 64, 256, 4, 2, 16, np.complex64, "slab"),
     ("fp16", 32, 128, 8, 0, 11, np.complex64, "fused"),
     ("fp32", 128, 512, 16, 2, 24, np.complex64, "slab"),
+    ("fp16", 64, 256, 8, 2, 16, np.complex64, "slab"),
 ])
 def test_factor_of_the_previous_interval_on_the_next(sched, K, Nbs, L, v, iters, io, form):
     """Gauss-Markov step (rho = J0(2 pi 1 kHz / 14 kHz)): the factor stored for
