@@ -62,7 +62,11 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
     static constexpr int PPW = (NTILE + NW - 1) / NW;
     // LDS: [main: Gram tiles, then the p / x exchange, then the staged outputs]
     //      [D: diagonal blocks] [T: T blocks, then M_d for the left form] [red]
-    static constexpr size_t sz_tiles = (size_t)NTILE * 2 * 256 * W;
+    // a tile plane in LDS: 16 rows of TR words (padded, so that reads down a
+    // column -- transposed tiles, the tile transform's operands -- are free of
+    // bank conflicts)
+    static constexpr int TR = 17, TP = 16 * TR;
+    static constexpr size_t sz_tiles = (size_t)NTILE * 2 * TP * W;
     static constexpr size_t PSZ = LOWP ? 2 : W;       // bytes of one exchanged p value
     static constexpr size_t sz_pb = 2 * (size_t)F * 2 * 4 * 64 * PSZ;   // [parity][slab][plane][elem][lane]
     static constexpr size_t sz_xb = (size_t)F * 2 * 4 * 64 * W;         // [slab][plane][elem][lane]
@@ -80,8 +84,9 @@ template <int KP_, int FMT_, int LB_> struct SlabCfg {
         size_t a = sz_tiles > sz_hstage ? sz_tiles : sz_hstage, b = sz_pb + (refresh ? sz_xb : 0), c = sz_stage(es);
         return a > b ? (a > c ? a : c) : (b > c ? b : c);
     }
-    // L = 8 and 16 keep C and T as 16-wide tiles (block diagonal for L = 8)
-    static constexpr int TS = LB >= 8 ? 16 : LB;
+    // L = 8 and 16 keep C and T as 16-wide tiles (block diagonal for L = 8),
+    // rows padded to TR words as the tiles of A
+    static constexpr int TS = LB >= 8 ? TR : LB;
     static constexpr size_t sz_d = LB ? 2 * W * KP * TS : 0;
     static constexpr size_t sz_t = LB ? 2 * W * KP * TS : 0;
     static constexpr size_t sz_red = 2 * 2 * (size_t)NW * 16 * W;      // [parity][value][wave][column]
@@ -316,8 +321,8 @@ void slab_kernel(const FusedParams P) {
                             ar = (16 * f1 + r < K) ? ar + s2w : (Wt)1;
                         }
                         nfa = fma(ar, (Wt)0, fma(ai, (Wt)0, nfa));
-                        sTile[((size_t)q * 2 + 0) * 256 + r * 16 + n] = ar;
-                        sTile[((size_t)q * 2 + 1) * 256 + r * 16 + n] = ai;
+                        sTile[((size_t)q * 2 + 0) * C::TP + r * C::TR + n] = ar;
+                        sTile[((size_t)q * 2 + 1) * C::TP + r * C::TR + n] = ai;
                     }
                 }
                 ++q;
@@ -359,7 +364,7 @@ void slab_kernel(const FusedParams P) {
     if constexpr (LB == 8 || LB == 16) {
         using OF = Op<F32, 1>;
         using f4 = typename OF::acc;
-        constexpr int TS = 16;                        // row stride of C and T in LDS (a tile's width)
+        constexpr int TS = C::TS;                     // row stride of C and T in LDS (a padded tile row)
         Wt* sCr = sD;                                 // C, rows 16 w + r: [KP][16] re, then im
         Wt* sCi = sD + KP * TS;
         Wt* sTr = sT;                                 // T, the same layout
@@ -368,6 +373,14 @@ void slab_kernel(const FusedParams P) {
         const int kb = n / LB, i = n % LB;            // block in the tile, row / column in the block
         const int bb = rb + kb * LB;                  // first row of the block
         const int o0 = kb * LB;                       // first column of the block in the tile
+        // the blocks of tile (w, w) are wave w's alone: its lanes exchange the
+        // factor's columns through LDS, whose operations a wave issues and
+        // completes in order; the fences keep the compiler from moving them
+        auto wave_sync = []() {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
         Wt tr[LB], ti[LB];
         bool blk_bad = false;
         if (P.T_in) {                                 // a given factor replaces the factorisation
@@ -384,8 +397,8 @@ void slab_kernel(const FusedParams P) {
             Wt ar[LB], ai[LB];
 #pragma unroll
             for (int c = 0; c < LB; ++c) {
-                ar[c] = sTile[((size_t)qd * 2 + 0) * 256 + n * 16 + o0 + c];
-                ai[c] = sTile[((size_t)qd * 2 + 1) * 256 + n * 16 + o0 + c];
+                ar[c] = sTile[((size_t)qd * 2 + 0) * C::TP + n * C::TR + o0 + c];
+                ai[c] = sTile[((size_t)qd * 2 + 1) * C::TP + n * C::TR + o0 + c];
             }
             Wt diag = 0;                              // a_ii, for the not-PD fallback
 #pragma unroll
@@ -400,11 +413,11 @@ void slab_kernel(const FusedParams P) {
                     const Wt l = sqrt(d);
                     if (g == 0) { sCr[(bb + j) * TS + o0 + j] = l; sCi[(bb + j) * TS + o0 + j] = (Wt)1 / l; }
                 }
-                __syncthreads();
+                wave_sync();
                 const Wt inv = sCi[(bb + j) * TS + o0 + j];
                 const Wt lr = ar[j] * inv, li = ai[j] * inv;
                 if (i > j && g == 0) { sCr[(bb + i) * TS + o0 + j] = lr; sCi[(bb + i) * TS + o0 + j] = li; }
-                __syncthreads();
+                wave_sync();
                 if (i > j) {
 #pragma unroll
                     for (int k = j + 1; k < LB; ++k) {   // a_ik -= l_ij conj(l_kj), needed for k <= i
@@ -476,15 +489,15 @@ void slab_kernel(const FusedParams P) {
                 for (int f = 1; f < F; ++f)
                     if (q >= tile_index(f, f, F)) a = f;
                 const int b = a + (q - tile_index(a, a, F));
-                Wt* tre = sTile + ((size_t)q * 2 + 0) * 256;
-                Wt* tim = sTile + ((size_t)q * 2 + 1) * 256;
+                Wt* tre = sTile + ((size_t)q * 2 + 0) * C::TP;
+                Wt* tim = sTile + ((size_t)q * 2 + 1) * C::TP;
                 // X = A_ab T_b^H: operand lane (g', n') holds A_ab[n'][4 e + g'] and
                 // conj(T_b[n'][4 e + g']) for contraction step e
                 f4 Xr = f4{0, 0, 0, 0}, Xi = f4{0, 0, 0, 0};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int j = 4 * e + g;
-                    const Wt a_r = tre[n * 16 + j], a_i = tim[n * 16 + j];
+                    const Wt a_r = tre[n * C::TR + j], a_i = tim[n * C::TR + j];
                     const Wt t_r = sTr[(16 * b + n) * TS + j], t_i = sTi[(16 * b + n) * TS + j];
                     Xr = OF::mfma(a_r, t_r, Xr);
                     Xr = OF::mfma(a_i, t_i, Xr);
@@ -505,8 +518,8 @@ void slab_kernel(const FusedParams P) {
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    tre[(4 * g + e) * 16 + n] = Ur[e];
-                    tim[(4 * g + e) * 16 + n] = Ui[e];
+                    tre[(4 * g + e) * C::TR + n] = Ur[e];
+                    tim[(4 * g + e) * C::TR + n] = Ui[e];
                 }
             }
         }
@@ -530,16 +543,16 @@ void slab_kernel(const FusedParams P) {
         // the conjugate of the upper one, the diagonal real
         {
             const int qd = tile_index(wave, wave, F);
-            Wt* tre = sTile + ((size_t)qd * 2 + 0) * 256;
-            Wt* tim = sTile + ((size_t)qd * 2 + 1) * 256;
+            Wt* tre = sTile + ((size_t)qd * 2 + 0) * C::TP;
+            Wt* tim = sTile + ((size_t)qd * 2 + 1) * C::TP;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int r = 4 * g + e;
                 if (r > n) {
-                    tre[r * 16 + n] = tre[n * 16 + r];
-                    tim[r * 16 + n] = -tim[n * 16 + r];
+                    tre[r * C::TR + n] = tre[n * C::TR + r];
+                    tim[r * C::TR + n] = -tim[n * C::TR + r];
                 } else if (r == n) {
-                    tim[r * 16 + n] = 0;
+                    tim[r * C::TR + n] = 0;
                 }
             }
         }
@@ -557,12 +570,12 @@ void slab_kernel(const FusedParams P) {
         const int fr = row >> 4, fc = c >> 4, rr = row & 15, cc = c & 15;
         if (fr <= fc) {
             const int q = tile_index(fr, fc, F);
-            re = sTile[((size_t)q * 2 + 0) * 256 + rr * 16 + cc];
-            im = sTile[((size_t)q * 2 + 1) * 256 + rr * 16 + cc];
+            re = sTile[((size_t)q * 2 + 0) * C::TP + rr * C::TR + cc];
+            im = sTile[((size_t)q * 2 + 1) * C::TP + rr * C::TR + cc];
         } else {
             const int q = tile_index(fc, fr, F);
-            re = sTile[((size_t)q * 2 + 0) * 256 + cc * 16 + rr];
-            im = -sTile[((size_t)q * 2 + 1) * 256 + cc * 16 + rr];
+            re = sTile[((size_t)q * 2 + 0) * C::TP + cc * C::TR + rr];
+            im = -sTile[((size_t)q * 2 + 1) * C::TP + cc * C::TR + rr];
         }
     };
     const int cstd = 16 * wave + n, cperm = 16 * wave + rho16(n);
@@ -1090,7 +1103,7 @@ void slab_kernel(const FusedParams P) {
     if constexpr (split && (LB == 8 || LB == 16)) {   // x = T_w^H x_bar on the matrix cores
         using OF = Op<F32, 1>;
         using f4 = typename OF::acc;
-        constexpr int TS = 16;
+        constexpr int TS = C::TS;
         const Wt* sTr = sT;
         const Wt* sTi = sT + KP * TS;
         const int rb = 16 * wave;
