@@ -676,6 +676,35 @@ def test_slab_form_matches_oracle(case):
     assert np.array_equal(fl, ref.flags.astype(np.int64))
 
 
+@pytest.mark.parametrize("K,L,sched", [(64, 0, "fp16"), (64, 4, "fp16"), (64, 8, "fp16"), (64, 16, "fp32"),
+                                        (128, 16, "fp32"), (128, 0, "fp64")])
+def test_slab_empty_batch_and_zero_iterations(K, L, sched):
+    """The slab form with B = 0 (a no-op) and with I = 0 (x_hat = 0 after
+    the setup, labels of 0, as the oracle's)."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    _say(f"case slab empty / I=0 K={K} L={L} {sched}")
+    ctx = fp.Context(0)
+    ctx.set_launch_form("slab")
+    dev = torch.device("cuda:0")
+    Nbs = 2 * K
+    H = torch.zeros((0, Nbs, K), dtype=torch.complex64, device=dev)
+    Y = torch.zeros((0, Nbs, 14), dtype=torch.complex64, device=dev)
+    s = torch.zeros((0,), dtype=torch.float64, device=dev)
+    x, lab, fl = fp.detect(H, Y, s, 16, 5, L, sched, variant=2 if L else 0, ctx=ctx)
+    torch.cuda.synchronize()
+    assert x.shape == (0, K, 14)
+    ctx.close()
+    wl = _wl(3, Nbs, K, 14, 16, 10.0, 0.3, 68)
+    x, lab, fl = _slab_run(wl, 16, 0, L, sched, np.complex64, 0, 2 if L else 0)
+    assert np.all(x == 0)
+    ref = oracle_detect(wl, 16, 0, L, sched, np.complex64, variant=2 if L else 0)
+    assert np.array_equal(lab, ref.labels)
+    assert np.array_equal(fl, ref.flags.astype(np.int64))
+
+
 @pytest.mark.parametrize("K,Nbs,L", [(64, 256, 16), (128, 512, 16), (80, 200, 16), (64, 256, 8)])
 def test_slab_fp32_l16_converged_within_1e5_of_lmmse(K, Nbs, L):
     """FP-BJ-CG with 16 x 16 (and 8 x 8) blocks and FP32 work run to
