@@ -162,7 +162,8 @@ void fpcg_destroy(fpcg_ctx* ctx);
  * which runs the workgroup of nw waves where that count is built for the
  * launch's shape class (each wave then holds K/(4 nw) entries of every
  * iterate per lane, so a Jacobi block must fit them), else the default count.
- *   FPCG_LAUNCH_SLAB       (K = 64 and K = 128; no refinement; L = 0 or 4)
+ *   FPCG_LAUNCH_SLAB       (K = 64 and K = 128; no refinement; L = 0 or 4,
+ *                          and L = 8 / 16 in the symmetric form)
  *                          K/16 waves per channel, each holding its slab of
  *                          rows of every iterate and its column slab of A in
  *                          registers (the operand copies of A p and of the
