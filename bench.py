@@ -875,6 +875,43 @@ def graph_timed(fn, steps, warmup, idle):
     return wall, np.array([a.elapsed_time(b) for a, b in ev])
 
 
+def interleaved_p50(fns, rounds=3, steps=20, warmup=3):
+    """Median kernel time of each launch fn(stream), each captured once in a
+    HIP graph and timed in interleaved rounds (every candidate once per
+    round), so that clock and thermal drift over the run does not favour the
+    candidate timed later.  Returns the median over rounds of each round's
+    median, in ms."""
+    import torch
+
+    graphs = []
+    for fn in fns:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn(side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        graphs.append(g)
+    stream = torch.cuda.current_stream()
+    res = [[] for _ in graphs]
+    for _ in range(rounds):
+        for k, g in enumerate(graphs):
+            for _ in range(warmup):
+                g.replay()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            for e0, e1 in ev:
+                e0.record(stream)
+                g.replay()
+                e1.record(stream)
+            torch.cuda.synchronize()
+            res[k].append(float(np.median([a.elapsed_time(b) for a, b in ev])))
+    return [float(np.median(r)) for r in res]
+
+
 def profile_run(args):
     """Short run for profilers: the launches of one schedule (--schedule, --L,
     --iters, --refresh, --refine, --variant; 'auto' = the workload's first
@@ -1081,12 +1118,13 @@ def batch_bench(args):
                 break
         if heur_cd is None:
             log(f"the heuristic's {hf} is not built for K={K}")
-    for cd in cands + ([heur_cd] if heur_cd else []):
+    timed = cands + ([heur_cd] if heur_cd else [])
+    for cd in timed:
         cd["iters"] = search(cd)
         cd["form"] = tune(cd, cd["iters"])
         cd["ber"] = ber_at(cd, cd["iters"], snr_op)
-        _, per = graph_timed(launcher(cd, cd["iters"]), 10, 3, 0.0)
-        cd["p50_ms"] = float(np.median(per))
+    for cd, t in zip(timed, interleaved_p50([launcher(cd, cd["iters"]) for cd in timed])):
+        cd["p50_ms"] = t
         log(f"  {cd['sched']} L={cd['L']} refresh={cd['refresh']} refine={cd['refine']} v{cd['variant']}: "
             f"I={cd['iters']} BER {cd['ber']:.2e}, kernel p50 {cd['p50_ms']:.4f} ms ({cd['form']})")
     # the headline: the fastest configured schedule that reaches BER parity;
