@@ -752,6 +752,36 @@ def test_slab_l16_not_pd_block_flagged_and_isolated(L, sched):
     _spread_parity(x[keep], ref2, sp2, sched, "not-PD neighbours", np.complex64)
 
 
+@pytest.mark.parametrize("K,L,sched,refresh", [(64, 4, "fp16", 4), (64, 8, "fp16", 4), (64, 16, "fp32", 0),
+                                              (128, 16, "fp32", 0), (64, 0, "fp64", 0)])
+def test_slab_run_to_run_bitwise_determinism(K, L, sched, refresh):
+    """The slab form gives the same bits on every run: its reductions over
+    lanes and waves, the LDS exchanges of p and x, and the L = 8 / 16 block
+    factorisation (whose steps a wave orders by itself, without a workgroup
+    barrier) have one fixed order.  A batch of 2000 channels, three runs."""
+    import torch
+
+    import paper_2504_09820_amd as fp
+
+    _say(f"case slab determinism K={K} L={L} {sched} refresh={refresh}")
+    wl = _wl(2000, 2 * K, K, 14, 64, 20.0, 0.6, 69)
+    dev = torch.device("cuda:0")
+    H = torch.from_numpy(wl.H.astype(np.complex64)).to(dev)
+    Y = torch.from_numpy(wl.Y.astype(np.complex64)).to(dev)
+    s2 = torch.from_numpy(wl.sigma2).to(dev)
+    ctx = fp.Context(0)
+    ctx.set_launch_form("slab")
+    outs = []
+    for _ in range(3):
+        x, lab, fl = fp.detect(H, Y, s2, 64, 12, L, sched, refresh_every=refresh, variant=2 if L else 0, ctx=ctx)
+        torch.cuda.synchronize()
+        outs.append((x.cpu().numpy().view(np.uint8), lab.cpu().numpy(), fl.cpu().numpy()))
+    ctx.close()
+    for o in outs[1:]:
+        for u, v in zip(outs[0], o):
+            assert np.array_equal(u, v)
+
+
 @pytest.mark.parametrize("K,Nbs,L", [(64, 256, 0), (64, 256, 4), (128, 512, 0)])
 def test_slab_fp64_converged_to_1e12(K, Nbs, L):
     _say(f"case slab fp64 converged K={K} L={L}")
