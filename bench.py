@@ -1190,6 +1190,9 @@ def batch_bench(args):
                      "p50_ms": round(float(np.median(per_h)), 5),
                      "value": round(B * R / (wall_h / max(5, args.steps // 4)), 1),
                      "speedup_vs_fp64_cg": round((wall_64 / steps64) / (wall_h / max(5, args.steps // 4)), 3)}
+        work_h = work_model(B, Nbs, K, R, heur_cd["L"], heur_cd["iters"], heur_cd["sched"], heur_cd["refresh"],
+                            heur_cd["refine"], 16 if io == np.complex128 else 8)
+        heur_line["roofline"] = roofline_of(work_h, heur_cd["sched"], float(np.mean(per_h)))
 
     # ---------------------------------------------------------------- roofline of the fused kernel
     kern_ms = float(np.mean(per_mp))
