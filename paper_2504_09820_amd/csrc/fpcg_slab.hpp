@@ -11,10 +11,14 @@
 //      the upper-triangle 16x16 tiles of A = H^H H + sigma^2 I are spread over
 //      the waves; every tile goes through LDS once and each wave reads its
 //      column slab back (tiles below the diagonal as conjugate transposes).
-//   2. Block-Jacobi setup (eq. pre_BJ) for L = 4: Cholesky of every 4 x 4
+//   2. Block-Jacobi setup (eq. pre_BJ).  L = 4: Cholesky of every 4 x 4
 //      diagonal block, T = C^{-1}; the symmetric form (the system of Thm 4)
 //      rewrites A <- T A T^H and b <- T b in registers (rows lane-local, columns
 //      across four adjacent lanes); Alg. 3 as printed keeps M_d = T^H T.
+//      L = 8 and 16 (symmetric form): the blocks tile the diagonal 16 x 16
+//      tiles; each wave factors those of its own tile, and every upper tile
+//      is rewritten in LDS as T_a A_ab T_b^H on the fp32 matrix cores before
+//      the waves read their column slabs.
 //   3. (P)CG (Alg. 2 / Alg. 3): A p on the matrix cores with A's operand copy
 //      in registers -- A p for rows of slab w contracts A's row slab w, which is
 //      the conjugate of the column slab the wave holds, so every operand
