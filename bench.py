@@ -66,8 +66,8 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     cs = os.path.join(ROOT, "paper_2504_09820_amd", "csrc")
     for f in sorted(os.listdir(cs)):
-        if not (f.startswith("fpcg_inst_") or f in ("fpcg_device.hpp", "fpcg_fused.hpp", "fpcg_host.hip",
-                                                     "fpcg_host.hpp", "fpcg_registry.hpp")):
+        if not (f.startswith("fpcg_inst_") or f in ("fpcg_device.hpp", "fpcg_fused.hpp", "fpcg_slab.hpp",
+                                                     "fpcg_host.hip", "fpcg_host.hpp", "fpcg_registry.hpp")):
             continue
         with open(os.path.join(cs, f), "rb") as fh:
             h.update(fh.read())
