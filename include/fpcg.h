@@ -222,9 +222,10 @@ fpcg_status fpcg_check(int64_t B, int32_t Nbs, int32_t K, int32_t R, int32_t qam
  *   symmetric form for fp16, bf16 and FP32 operands (two blocks per tile).
  *   65 <= K <= 128 is built for fp8, fp16 and bf16 operands, left block-Jacobi
  *   forms (variant 0 or 1) and no FP64 refresh (with fp8 also with FP64
- *   refinement), for FP64 operands without a preconditioner and for FP32
- *   operands without one or with L = 16 in the symmetric form (the slab
- *   form).  Other combinations return FPCG_E_UNSUPPORTED.
+ *   refinement), and in the slab form for FP64 and FP32 operands without a
+ *   preconditioner and for FP32, fp16 and bf16 operands with L = 16 in the
+ *   symmetric form, with or without the FP64 refresh.  Other combinations
+ *   return FPCG_E_UNSUPPORTED.
  *   sched = NULL selects the schedule by the precision heuristic (eq.
  *   heuristic for block_L = 0, eq. heuristic_bj otherwise): with kappa the
  *   expected condition number the context holds for (Nbs, K, block_L)

@@ -114,7 +114,8 @@ void add_slab_entry(std::vector<KernelEntry>& v) {
     e.kind = 1;
     e.arow = 0;
     e.lds = [](bool sp, bool, int f) -> size_t { return C::lds(sizeof(IOT) * 2, LB > 0 && sp, f > 0); };
-    constexpr bool RFB = FMT != F64 && KP == 64;       // refresh builds: reduced formats at K = 64
+    // refresh builds: FP32 and reduced formats at K = 64, and at K = 128 with L = 16
+    constexpr bool RFB = FMT != F64 && (KP == 64 || LB == 16);
     if constexpr (LB >= 8) {                           // L = 8 and 16: the symmetric form only
         e.fn[0][0] = e.fn[0][1] = nullptr;
         e.launch[0][0] = e.launch[0][1] = nullptr;

@@ -641,6 +641,9 @@ SLAB_CASES = [
     ("K48-N200-R9-fp32-L16-c128", 48, 200, 9, 16, 14, 16, "fp32", np.complex128, 0, 2),
     ("K128-fp32-L16-split", 128, 512, 14, 256, 24, 16, "fp32", np.complex64, 0, 2),
     ("K112-N300-R17-fp32-L16", 112, 300, 17, 64, 20, 16, "fp32", np.complex64, 0, 2),
+    ("K128-fp32-L16-split-refresh4", 128, 512, 14, 256, 16, 16, "fp32", np.complex64, 4, 2),
+    ("K128-fp16-L16-split-refresh4", 128, 512, 14, 256, 16, 16, "fp16", np.complex64, 4, 2),
+    ("K112-N300-bf16-L16-split-c128", 112, 300, 14, 64, 16, 16, "bf16", np.complex128, 0, 2),
 ]
 
 

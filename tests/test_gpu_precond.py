@@ -53,6 +53,7 @@ ROUND_TRIP = [
     ("slab", "bf16", 64, 256, 20, 4, 1, np.complex64),
     ("slab", "fp32", 64, 256, 14, 16, 2, np.complex64),
     ("slab", "fp16", 64, 256, 14, 8, 2, np.complex64),
+    ("slab", "fp16", 128, 512, 14, 16, 2, np.complex64),
     ("slab", "fp32", 56, 200, 20, 8, 2, np.complex128),
     ("slab", "fp32", 128, 512, 14, 16, 2, np.complex128),
 ]
