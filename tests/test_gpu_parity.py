@@ -812,13 +812,15 @@ def test_slab_isolates_nonfinite_and_zero_channels():
 # (config, schedule, L, I, refresh, variant): the slab-form launches the
 # benchmark times at c3 and c4 -- the configured FP-BJ-CG schedule, the
 # heuristic's pick and FP64 CG, at the iteration counts the BER-parity
-# search settles on
+# search settles on (and at c4 fp16 with the FP64 refresh, reported beside
+# them)
 TIMED_FULL = [
     ("c3", "fp16", 4, 20, 4, 2),
     ("c3", "fp32", 4, 20, 0, 2),
     ("c3", "fp64", 0, 27, 0, 0),
-    ("c4", "fp32", 0, 130, 0, 0),
+    ("c4", "fp32", 16, 64, 0, 2),
     ("c4", "fp64", 0, 92, 0, 0),
+    ("c4", "fp16", 16, 67, 4, 2),
 ]
 _FULL_WL = {}
 
