@@ -145,6 +145,12 @@ void slab_kernel(const FusedParams P) {
     const bool colv = col < P.R;
     const int K = P.K, Nbs = P.Nbs, R = P.R;
     const bool refresh = RFR && P.refresh_every > 0;   // RFR: built with the FP64 refresh
+    // Issue priorities among the co-resident workgroups of a CU: the Gram's
+    // stream (latency-bound) at 1; the matrix-core throughput work at 0 --
+    // the FP64 refresh products, or, without the refresh, the iterations of
+    // the reduced and FP32 formats.  (Measured: c3 fp16 with the refresh and
+    // FP32 3-4 % faster; FP64 CG slower with it, so FP64 keeps one level.)
+    if constexpr (FMT != F64) __builtin_amdgcn_s_setprio(1);
 
     unsigned char* smain = smem;
     const size_t main_bytes = C::sz_main(ES, refresh);
@@ -952,6 +958,8 @@ void slab_kernel(const FusedParams P) {
         if (__ballot((myflag >> b) & 1u) != 0) wflag |= 1u << b;
     myflag = 0u;
     bool live = true, broken = false;
+    if constexpr (FMT != F64)
+        if (!refresh) __builtin_amdgcn_s_setprio(0);
     for (int it = 1; it <= P.iters; ++it) {
         // ---- varpi = A p   [u_MV]
         Wt wr[4], wi[4];
@@ -1021,6 +1029,11 @@ void slab_kernel(const FusedParams P) {
                 sXB[(((size_t)wave * 2 + 1) * 4 + e) * 64 + lane] = xi[e];
             }
             __syncthreads();
+            // the refresh's FP64 products are throughput work: its waves issue
+            // at the lowest priority, so that the latency-bound phases of
+            // co-resident workgroups (the Gram's loads and products, the
+            // iterations' chains) take the matrix cores between them
+            __builtin_amdgcn_s_setprio(0);
             // three real products per complex one: with the row of A as
             // a_r - i a_i, Re = P1 + P2 and Im = P3 + (P2 - P1) for P1 = a_r x_r,
             // P2 = a_i x_i, P3 = (a_r - a_i)(x_r + x_i); two passes, so that
@@ -1072,6 +1085,7 @@ void slab_kernel(const FusedParams P) {
             }
             // (the x exchange is next written at the next refresh, at least
             // three barriers later, so no barrier is needed after the reads)
+            __builtin_amdgcn_s_setprio(1);
         }
         // ---- z = M r (left form) or r, rho_i, beta, p
         Wt zr[4], zi[4];
