@@ -755,6 +755,9 @@ CONFIGURED = {
 }
 # fixed iteration count where the workload states one (c1: 8)
 FIXED_ITERS = {"c1": 8}
+# SNR sweeps a workload states (c2: 0-20 dB in 2 dB steps): the BER of every
+# timed schedule at its BER-parity iteration count over the sweep
+SNR_SWEEP = {"c2": [float(s) for s in range(0, 21, 2)]}
 
 
 def work_model(B, Nbs, K, R, L, iters, sched, refresh=0, refine=0, elem=8):
@@ -1158,6 +1161,16 @@ def batch_bench(args):
         curves["fp64_cg"].append((sn, ber_at(F64, I64, sn)))
         curves["mixed"].append((sn, ber_at(best, best["iters"], sn)))
     snr_at = {k: crossing(v) for k, v in curves.items()}
+    sweep = None
+    if args.config in SNR_SWEEP:
+        sweep = []
+        for sd in SNR_SWEEP[args.config]:
+            row = {"snr_db": sd, "fp64_cg": ber_at(F64, I64, sd)}
+            for cd in timed:
+                row[f"{cd['sched']}_L{cd['L']}_I{cd['iters']}"] = ber_at(cd, cd["iters"], sd)
+            sweep.append(row)
+        log("BER over the stated SNR sweep: " + "; ".join(
+            f"{r['snr_db']:.0f} dB " + " ".join(f"{k} {v:.3e}" for k, v in r.items() if k != "snr_db") for r in sweep))
     gap64 = None if None in (snr_at["mixed"], snr_at["fp64_cg"]) else snr_at["mixed"] - snr_at["fp64_cg"]
     gapc = None if None in (snr_at["mixed"], snr_at["converged"]) else snr_at["mixed"] - snr_at["converged"]
     log(f"SNR at BER 1e-3: converged {snr_at['converged']}, FP64 CG {snr_at['fp64_cg']}, {best['sched']} "
@@ -1275,7 +1288,8 @@ def batch_bench(args):
                 "converged_fp64": berconv, "fp64_cg": ber64, "mixed": best["ber"],
                 "snr_db_at_1e-3": {k: (None if v is None else round(v, 3)) for k, v in snr_at.items()},
                 "gap_db_vs_fp64_cg": None if gap64 is None else round(gap64, 3),
-                "gap_db_vs_converged": None if gapc is None else round(gapc, 3)},
+                "gap_db_vs_converged": None if gapc is None else round(gapc, 3),
+                "snr_sweep": sweep},
         "candidates": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in cd.items()} for cd in cands],
         "heuristic": {"picks": list(heur.values()), "timed_pick": heur_line},
         "block_size_rule": rule,
