@@ -97,6 +97,25 @@ def test_check_large_k(fp):
     assert fp.check(5, 256, 32, 14, 64, 16, 16, fp.schedule("fp16")) == 0      # L = 16 runs the K <= 128 build
 
 
+def test_check_slab_block_sizes(fp):
+    """The slab form's block-Jacobi builds: L = 8 (K <= 64) and L = 16 in the
+    symmetric form only, with or without the FP64 refresh; L = 16 at
+    K = 128 for fp32, fp16 and bf16 but not fp8 or FP64."""
+    sch = fp.schedule
+    assert fp.check(5, 256, 64, 14, 64, 16, 8, sch("fp16", refresh_every=4, variant=2)) == 0
+    assert fp.check(5, 256, 56, 14, 64, 16, 8, sch("fp32", variant=2)) == 0
+    assert fp.check(5, 256, 64, 14, 64, 16, 16, sch("fp32", variant=2)) == 0
+    assert fp.check(5, 256, 64, 14, 64, 16, 16, sch("fp32", refresh_every=3, variant=2)) == 0
+    for f in ("fp32", "fp16", "bf16"):
+        assert fp.check(5, 512, 128, 14, 256, 16, 16, sch(f, variant=2)) == 0
+        assert fp.check(5, 512, 128, 14, 256, 16, 16, sch(f, refresh_every=4, variant=2)) == 0
+        assert fp.check(5, 512, 112, 14, 256, 16, 16, sch(f, variant=2)) == 0
+    assert fp.check(5, 512, 128, 14, 256, 16, 16, sch("fp32", variant=0)) == -4     # no left form there
+    assert fp.check(5, 512, 128, 14, 256, 16, 16, sch("fp16", refresh_every=4, variant=0)) == -4
+    assert fp.check(5, 512, 128, 14, 256, 16, 16, sch("fp64", variant=2)) == -4
+    assert fp.check(5, 512, 128, 14, 256, 16, 8, sch("fp32", variant=2)) == -4
+
+
 def test_check_rejects_bad_schedules(fp):
     S = fp.Schedule
     assert fp.check(4, 64, 8, 1, 16, 8, 0, S(9, 9, 1, 1, 0, 0, 0)) == -1
