@@ -154,8 +154,8 @@ void slab_kernel(const FusedParams P) {
 
     unsigned char* smain = smem;
     const size_t main_bytes = C::sz_main(ES, refresh);
-    Wt* sD = reinterpret_cast<Wt*>(smem + main_bytes);                 // [K][L] re, then im
-    Wt* sT = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d);       // T blocks [K][L] re, im
+    Wt* sD = reinterpret_cast<Wt*>(smem + main_bytes);                 // [KP][TS] re, then im
+    Wt* sT = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d);       // T blocks [KP][TS] re, im
     Wt* sM = sT + 2 * KP * (LB ? C::TS : 1);                             // left form: M_d blocks
     Wt* sRed = reinterpret_cast<Wt*>(smem + main_bytes + C::sz_d + (split ? 1 : 2) * C::sz_t);
     __shared__ uint32_t sFlag;
@@ -375,7 +375,7 @@ void slab_kernel(const FusedParams P) {
         using OF = Op<F32, 1>;
         using f4 = typename OF::acc;
         constexpr int TS = C::TS;                     // row stride of C and T in LDS (a padded tile row)
-        Wt* sCr = sD;                                 // C, rows 16 w + r: [KP][16] re, then im
+        Wt* sCr = sD;                                 // C, rows 16 w + r: [KP][TS] re, then im
         Wt* sCi = sD + KP * TS;
         Wt* sTr = sT;                                 // T, the same layout
         Wt* sTi = sT + KP * TS;
